@@ -1,0 +1,152 @@
+/*
+ * ranphy.h — C ABI of libranphy, the MI355X (gfx950) uplink receive hot path.
+ *
+ * The three calls are the data-parallel steps of a software-defined DU's uplink PHY that
+ * the paper accelerates with SIMD (Sec. III-B: channel estimation and MIMO detection;
+ * Sec. IV and Fig. 4: LMMSE detection built from a factorisation of the covariance and
+ * forward/backward substitution):
+ *
+ *   ranphy_chest_ls     DMRS least-squares channel estimate (+ frequency interpolation)
+ *   ranphy_mmse_detect  channel interpolation, Gram H^H H + s2 I, Cholesky factorisation,
+ *                       matched filter, forward/back substitution, unbiasing
+ *   ranphy_llr_demap    max-log LLR soft demapping, QPSK .. 256QAM
+ *
+ * Conventions shared by every call
+ *   - Complex values are interleaved float pairs (re, im) ("complex64"); every buffer is
+ *     row-major with the slot index outermost.
+ *   - All buffers are device memory allocated by the caller, at least 8-byte aligned
+ *     (256-byte alignment recommended).  The library allocates nothing, keeps no pointer
+ *     after returning and holds no global mutable state: calls are thread-safe.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ *     asynchronous: the call returns once the kernels are launched.
+ *   - The descriptor and sizes are validated on the host before any launch; invalid input
+ *     returns a negative status and touches no memory.  Nothing throws across the ABI.
+ *   - Per-element numerical failure is not an error: where the regularised Gram matrix is
+ *     not numerically positive definite (possible only with s2 = 0 and a rank-deficient
+ *     channel) the detector writes NaN symbols and +inf post-equalisation variance for
+ *     that resource element.
+ *
+ * DMRS structure (the paper gives none; the 3GPP NR shape is used): port p occupies
+ * subcarriers k = (p mod C) + C j of every DMRS symbol, j < ceil(n_sc / C); occasion o spans
+ * symbols dmrs_sym0[o] .. dmrs_sym0[o] + T - 1, T in {1, 2}; with T = 2, ports p and p + C
+ * share a comb offset and are separated by a time cover code contained in the pilot values
+ * the caller passes.  Layers map one-to-one onto ports 0 .. n_layers-1, so n_layers <= C T.
+ * Symbols of a DMRS occasion carry no data; "dsym" enumerates the remaining symbols in
+ * ascending order.
+ */
+#ifndef RANPHY_H
+#define RANPHY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RANPHY_ABI_VERSION 1
+
+#if defined(__GNUC__) || defined(__clang__)
+#define RANPHY_API __attribute__((visibility("default")))
+#else
+#define RANPHY_API
+#endif
+
+/* Shape of a batch of slots; every slot in the batch has the same shape. */
+typedef struct ranphy_slot_desc {
+  int32_t n_prb;        /* resource blocks, 1..275; n_sc = 12 n_prb subcarriers       */
+  int32_t n_symb;       /* OFDM symbols per slot, 1..14                                */
+  int32_t n_rx;         /* receive antennas, 1..64                                     */
+  int32_t n_layers;     /* layers, 1..16, <= n_rx and <= dmrs_comb * dmrs_td          */
+  int32_t qm;           /* bits per symbol: 2 QPSK, 4 16QAM, 6 64QAM, 8 256QAM        */
+  int32_t dmrs_comb;    /* comb C: 2, 4 or 8                                           */
+  int32_t dmrs_td;      /* symbols per DMRS occasion T: 1 or 2                         */
+  int32_t n_occ;        /* DMRS occasions, 1..4                                        */
+  int32_t dmrs_sym0[4]; /* first symbol of each occasion, ascending, non-overlapping  */
+  int32_t n_slots;      /* slots in the batch, >= 0 (0 is a no-op)                     */
+} ranphy_slot_desc;
+
+/* Resolution of a channel-estimate buffer. */
+enum {
+  RANPHY_H_PILOT = 0, /* [slot][occ][j][rx][layer], j < ceil(n_sc / C): the estimate on the
+                         layer's own pilot subcarrier (p mod C) + C j; unused tail entries
+                         (j past the layer's last pilot) are written as 0 and never read  */
+  RANPHY_H_FULL = 1   /* [slot][occ][sc][rx][layer]: interpolated to every subcarrier     */
+};
+
+/* Status codes. */
+enum {
+  RANPHY_OK = 0,
+  RANPHY_ERR_INVALID = -1,     /* NULL or misaligned pointer, bad descriptor field      */
+  RANPHY_ERR_UNSUPPORTED = -2, /* well-formed but outside the supported shapes          */
+  RANPHY_ERR_LAUNCH = -3       /* the HIP runtime refused a launch (no device, ...)     */
+};
+
+/* Buffer identifiers for ranphy_buffer_floats. */
+enum {
+  RANPHY_BUF_RX = 0,        /* [slot][symb][sc][rx]           complex64 */
+  RANPHY_BUF_PILOTS = 1,    /* [slot][occ][t][j][layer]       complex64 */
+  RANPHY_BUF_H = 2,         /* see RANPHY_H_PILOT / RANPHY_H_FULL        */
+  RANPHY_BUF_NOISE_VAR = 3, /* [slot]                         float     */
+  RANPHY_BUF_X = 4,         /* [slot][dsym][sc][layer]        complex64 */
+  RANPHY_BUF_NV = 5,        /* [slot][dsym][sc][layer]        float     */
+  RANPHY_BUF_LLR = 6        /* [slot][dsym][sc][layer][qm]    float     */
+};
+
+/* ABI version the library was built with (RANPHY_ABI_VERSION). */
+RANPHY_API int ranphy_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+RANPHY_API const char* ranphy_status_str(int status);
+
+/* Number of floats (a complex value counts 2) in buffer `buf` for descriptor `d`
+ * (h_res matters only for RANPHY_BUF_H); a negative status if `d` is invalid. */
+RANPHY_API int64_t ranphy_buffer_floats(const ranphy_slot_desc* d, int buf, int h_res);
+
+/*
+ * DMRS least-squares channel estimate (Sec. III-B names channel estimation as a block
+ * suited to data-parallel execution; the estimator is the standard LS one).
+ *   h(o, j, r, p) = (1/T) sum_{t<T} rx(dmrs_sym0[o] + t, k, r) conj(pilots(o, t, j, p)),
+ *   k = (p mod C) + C j.
+ * With h_res = RANPHY_H_FULL the estimate is interpolated linearly in frequency between the
+ * layer's consecutive pilots and held at the nearest pilot outside the first/last one.
+ *   rx      in  [slot][symb][sc][rx] complex64
+ *   pilots  in  [slot][occ][t][j][layer] complex64 (unit modulus, cover code included)
+ *   h       out per h_res, complex64
+ */
+RANPHY_API int ranphy_chest_ls(const ranphy_slot_desc* d, const float* rx, const float* pilots, float* h,
+                    int h_res, void* stream);
+
+/*
+ * Linear MMSE detection per data resource element (Sec. IV, Fig. 4: LMMSE detection with a
+ * triangular factorisation of the covariance and forward/backward substitution; here the
+ * layer-domain covariance G = H^H H + s2 I, factorised by Cholesky).
+ *   H      channel at (sc, symbol): frequency interpolation of h (PILOT) or h itself (FULL),
+ *          then linear interpolation in the symbol index between occasion centres
+ *          dmrs_sym0[o] + (T-1)/2, held outside them (a single occasion is held).
+ *   x_hat  = G^-1 H^H y,  mu_l = 1 - s2 (G^-1)_ll,
+ *   x      = x_hat / mu (unbiased),  nv = (1 - mu) / mu  (post-equalisation noise plus
+ *          interference variance of the unbiased estimate, unit-energy layers).
+ *   rx         in  [slot][symb][sc][rx] complex64
+ *   h          in  per h_res, complex64
+ *   noise_var  in  [slot] float, s2 >= 0 (noise variance per receive antenna and RE)
+ *   x          out [slot][dsym][sc][layer] complex64
+ *   nv         out [slot][dsym][sc][layer] float
+ */
+RANPHY_API int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
+                       const float* noise_var, float* x, float* nv, void* stream);
+
+/*
+ * Max-log LLRs of Gray square QAM (3GPP NR mapping structure: bits b0, b2, .. on the
+ * in-phase axis, b1, b3, .. on the quadrature axis), unit average energy:
+ *   llr_b = (min_{s: b=1} |x - s|^2 - min_{s: b=0} |x - s|^2) / nv,  positive favours 0.
+ *   x    in  [slot][dsym][sc][layer] complex64
+ *   nv   in  [slot][dsym][sc][layer] float (> 0; 0 gives +-inf, NaN on a tie)
+ *   llr  out [slot][dsym][sc][layer][qm] float
+ */
+RANPHY_API int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const float* nv, float* llr,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

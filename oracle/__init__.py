@@ -165,6 +165,11 @@ def llr_batch(x: np.ndarray, nv, qm: int) -> np.ndarray:
     return llr
 
 
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().ranphy_ref_threads())
+
+
 def qam_points(qm: int) -> np.ndarray:
     pts = np.zeros(1 << qm, np.complex128)
     _check(lib().ranphy_ref_qam_points(qm, _ptr(pts)), "qam_points")

@@ -24,6 +24,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 
@@ -31,6 +34,15 @@ typedef double complex cplx;
 #define REF_MAX_L 16
 
 int ranphy_ref_version(void) { return 1; }
+
+/* Threads an OpenMP loop of this library runs on (1 when built without OpenMP). */
+int ranphy_ref_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------------------- */
 /* Descriptor helpers.                                                                    */

@@ -61,6 +61,7 @@ enum { RANPHY_REF_H_PILOT = 0, RANPHY_REF_H_FULL = 1 };
 enum { RANPHY_REF_ROUTE_LU = 0, RANPHY_REF_ROUTE_RCOV = 1 };
 
 int ranphy_ref_version(void);
+int ranphy_ref_threads(void);
 
 /* Slot-level calls (host pointers). */
 int ranphy_ref_chest_ls(const ranphy_ref_desc* d, const float* rx, const float* pilots,

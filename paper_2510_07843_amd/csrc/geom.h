@@ -1,0 +1,76 @@
+// Slot geometry shared by the host layer and the kernels of libranphy.
+//
+// The host validates a ranphy_slot_desc once and derives everything a kernel needs:
+// subcarrier and pilot counts, the list of data symbols and, per data symbol, the two
+// DMRS occasions and the weight of the linear time interpolation.  The struct is passed
+// to every kernel by value (it lives in the kernel-argument segment, read through the
+// scalar cache).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ranphy {
+
+constexpr int kMaxSymb = 14;
+constexpr int kMaxRx = 64;
+constexpr int kMaxLayers = 16;
+
+struct Geom {
+  int n_slots;
+  int n_symb;
+  int n_sc;
+  int n_rx;
+  int n_layers;
+  int qm;
+  int comb;     // C
+  int td;       // T
+  int n_occ;
+  int n_pilot;  // ceil(n_sc / C)
+  int n_dsym;
+  int sym0[4];
+  int dsym[16];     // data symbol indices, ascending
+  int t_o0[16];     // per data symbol: occasion before ...
+  int t_o1[16];     // ... and after it
+  float t_w[16];    // weight of t_o1: H = H_o0 + t_w (H_o1 - H_o0)
+};
+
+// Frequency interpolation rule for layer (port) p at subcarrier k: the two pilot indices
+// of that port and the weight a of the second one.  Linear between the port's consecutive
+// pilots at k = c + C j (c = p mod C), nearest pilot held outside the first and last one.
+__device__ __forceinline__ void freq_rule(const Geom& g, int p, int k, int& j0, int& j1,
+                                          float& a) {
+  const int C = g.comb;
+  const int c = p & (C - 1);
+  const int jp = (g.n_sc - c + C - 1) / C;
+  const int last = c + C * (jp - 1);
+  if (k <= c) {
+    j0 = j1 = 0;
+    a = 0.f;
+  } else if (k >= last) {
+    j0 = j1 = jp - 1;
+    a = 0.f;
+  } else {
+    j0 = (k - c) / C;
+    j1 = j0 + 1;
+    a = (float)(k - c - C * j0) / (float)C;
+  }
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Kernel launchers (one translation unit each).  They return a hipError_t.
+hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots, float2* h,
+                           int h_res, hipStream_t s);
+hipError_t launch_mmse_re(const Geom& g, const float2* rx, const float2* h, int h_res,
+                          const float* noise_var, float2* x, float* nv, hipStream_t s);
+hipError_t launch_llr_demap(const Geom& g, const float2* x, const float* nv, float* llr,
+                            hipStream_t s);
+
+}  // namespace ranphy

@@ -1,0 +1,173 @@
+// libranphy host layer: descriptor validation, geometry derivation, kernel dispatch.
+//
+// Everything here runs on the host before any launch, so every error path can be
+// exercised without a GPU.  The library allocates nothing and keeps no state between
+// calls.
+#include <stdint.h>
+
+#include "geom.h"
+#include "ranphy.h"
+
+namespace ranphy {
+
+hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
+                            const float* noise_var, float2* x, float* nv, hipStream_t s);
+bool mmse_mfma_eligible(const Geom& g);
+
+namespace {
+
+bool is_pow2_comb(int c) { return c == 2 || c == 4 || c == 8; }
+
+// Validate `d` and fill `g`; returns a ranphy status.
+int make_geom(const ranphy_slot_desc* d, Geom* g) {
+  if (!d) return RANPHY_ERR_INVALID;
+  if (d->n_slots < 0 || d->n_prb < 1 || d->n_prb > 275) return RANPHY_ERR_INVALID;
+  if (d->n_symb < 1 || d->n_symb > kMaxSymb) return RANPHY_ERR_INVALID;
+  if (d->n_rx < 1 || d->n_layers < 1) return RANPHY_ERR_INVALID;
+  if (d->qm != 2 && d->qm != 4 && d->qm != 6 && d->qm != 8) return RANPHY_ERR_INVALID;
+  if (!is_pow2_comb(d->dmrs_comb)) return RANPHY_ERR_INVALID;
+  if (d->dmrs_td != 1 && d->dmrs_td != 2) return RANPHY_ERR_INVALID;
+  if (d->n_occ < 1 || d->n_occ > 4) return RANPHY_ERR_INVALID;
+  for (int o = 0; o < d->n_occ; ++o) {
+    if (d->dmrs_sym0[o] < 0 || d->dmrs_sym0[o] + d->dmrs_td > d->n_symb) return RANPHY_ERR_INVALID;
+    if (o > 0 && d->dmrs_sym0[o] < d->dmrs_sym0[o - 1] + d->dmrs_td) return RANPHY_ERR_INVALID;
+  }
+  if (d->n_rx > kMaxRx || d->n_layers > kMaxLayers) return RANPHY_ERR_UNSUPPORTED;
+  if (d->n_layers > d->n_rx) return RANPHY_ERR_UNSUPPORTED;
+  if (d->n_layers > d->dmrs_comb * d->dmrs_td) return RANPHY_ERR_UNSUPPORTED;
+
+  Geom z = {};
+  z.n_slots = d->n_slots;
+  z.n_symb = d->n_symb;
+  z.n_sc = 12 * d->n_prb;
+  z.n_rx = d->n_rx;
+  z.n_layers = d->n_layers;
+  z.qm = d->qm;
+  z.comb = d->dmrs_comb;
+  z.td = d->dmrs_td;
+  z.n_occ = d->n_occ;
+  z.n_pilot = (z.n_sc + z.comb - 1) / z.comb;
+  double centre[4];
+  for (int o = 0; o < z.n_occ; ++o) {
+    z.sym0[o] = d->dmrs_sym0[o];
+    centre[o] = d->dmrs_sym0[o] + 0.5 * (d->dmrs_td - 1);
+  }
+  z.n_dsym = 0;
+  for (int s = 0; s < z.n_symb; ++s) {
+    bool dmrs = false;
+    for (int o = 0; o < z.n_occ; ++o) dmrs = dmrs || (s >= z.sym0[o] && s < z.sym0[o] + z.td);
+    if (dmrs) continue;
+    const int di = z.n_dsym++;
+    z.dsym[di] = s;
+    // Linear interpolation in time between occasion centres, held outside them.
+    int o0 = 0, o1 = 0;
+    double w = 0.0;
+    if (z.n_occ > 1 && s > centre[0]) {
+      if (s >= centre[z.n_occ - 1]) {
+        o0 = o1 = z.n_occ - 1;
+      } else {
+        for (int o = 0; o + 1 < z.n_occ; ++o)
+          if (s >= centre[o] && s < centre[o + 1]) {
+            o0 = o;
+            o1 = o + 1;
+            w = (s - centre[o]) / (centre[o + 1] - centre[o]);
+          }
+      }
+    }
+    z.t_o0[di] = o0;
+    z.t_o1[di] = o1;
+    z.t_w[di] = (float)w;
+  }
+  if (z.n_dsym == 0) return RANPHY_ERR_INVALID;
+  *g = z;
+  return RANPHY_OK;
+}
+
+bool aligned8(const void* p) { return p != nullptr && ((uintptr_t)p & 7u) == 0; }
+
+int status_of(hipError_t e) { return e == hipSuccess ? RANPHY_OK : RANPHY_ERR_LAUNCH; }
+
+}  // namespace
+}  // namespace ranphy
+
+using ranphy::Geom;
+
+extern "C" {
+
+int ranphy_abi_version(void) { return RANPHY_ABI_VERSION; }
+
+const char* ranphy_status_str(int status) {
+  switch (status) {
+    case RANPHY_OK: return "ok";
+    case RANPHY_ERR_INVALID: return "invalid argument (descriptor field, NULL or misaligned pointer)";
+    case RANPHY_ERR_UNSUPPORTED: return "unsupported shape";
+    case RANPHY_ERR_LAUNCH: return "HIP kernel launch failed";
+    default: return "unknown status";
+  }
+}
+
+int64_t ranphy_buffer_floats(const ranphy_slot_desc* d, int buf, int h_res) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  const int64_t S = g.n_slots;
+  switch (buf) {
+    case RANPHY_BUF_RX: return 2 * S * g.n_symb * g.n_sc * g.n_rx;
+    case RANPHY_BUF_PILOTS: return 2 * S * g.n_occ * g.td * g.n_pilot * g.n_layers;
+    case RANPHY_BUF_H:
+      if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+      return 2 * S * g.n_occ * (h_res == RANPHY_H_PILOT ? g.n_pilot : g.n_sc) * g.n_rx * g.n_layers;
+    case RANPHY_BUF_NOISE_VAR: return S;
+    case RANPHY_BUF_X: return 2 * S * g.n_dsym * g.n_sc * g.n_layers;
+    case RANPHY_BUF_NV: return S * g.n_dsym * g.n_sc * g.n_layers;
+    case RANPHY_BUF_LLR: return S * g.n_dsym * g.n_sc * g.n_layers * g.qm;
+    default: return RANPHY_ERR_INVALID;
+  }
+}
+
+int ranphy_chest_ls(const ranphy_slot_desc* d, const float* rx, const float* pilots, float* h,
+                    int h_res, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (!ranphy::aligned8(rx) || !ranphy::aligned8(pilots) || !ranphy::aligned8(h))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(ranphy::launch_chest_ls(
+      g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(pilots),
+      reinterpret_cast<float2*>(h), h_res, static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
+                       const float* noise_var, float* x, float* nv, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (!ranphy::aligned8(rx) || !ranphy::aligned8(h) || !ranphy::aligned8(x) ||
+      !ranphy::aligned8(nv) || noise_var == nullptr || ((uintptr_t)noise_var & 3u))
+    return RANPHY_ERR_INVALID;
+  const float2* rx2 = reinterpret_cast<const float2*>(rx);
+  const float2* h2 = reinterpret_cast<const float2*>(h);
+  float2* x2 = reinterpret_cast<float2*>(x);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ranphy::mmse_mfma_eligible(g))
+    return ranphy::status_of(ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, s));
+  return ranphy::status_of(ranphy::launch_mmse_re(g, rx2, h2, h_res, noise_var, x2, nv, s));
+}
+
+int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const float* nv, float* llr,
+                     void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (!ranphy::aligned8(x) || !ranphy::aligned8(nv) || !ranphy::aligned8(llr))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(ranphy::launch_llr_demap(g, reinterpret_cast<const float2*>(x), nv,
+                                                    llr, static_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

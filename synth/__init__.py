@@ -229,8 +229,10 @@ def rayleigh_flat(rng: np.random.Generator, shape_prefix: Sequence[int]) -> np.n
 
 
 def awgn(rng: np.random.Generator, shape_prefix: Sequence[int], noise_var: float) -> np.ndarray:
-    s = math.sqrt(noise_var / 2.0)
-    return (rng.standard_normal(tuple(shape_prefix)) + 1j * rng.standard_normal(tuple(shape_prefix))) * s
+    """CN(0, noise_var) samples as complex64 (drawn in float32 pairs)."""
+    w = rng.standard_normal(tuple(shape_prefix) + (2,), dtype=np.float32)
+    w *= np.float32(math.sqrt(noise_var / 2.0))
+    return w.view(np.complex64)[..., 0]
 
 
 # ---------------------------------------------------------------------------------------
@@ -273,20 +275,22 @@ def make_slot(shape: SlotShape, rng: np.random.Generator, scs_hz: float, pdp, sn
     else:
         h = channel
     X = transmit_grid(shape, pilots, x)
-    y = np.matmul(h, X.transpose(1, 2, 0)).transpose(2, 0, 1)  # [symb][sc][rx]
+    y = np.matmul(h, X.transpose(1, 2, 0)).transpose(2, 0, 1).astype(np.complex64)  # [symb][sc][rx]
     noise_var = 10.0 ** (-snr_db / 10.0)
     if not noiseless:
-        y = y + awgn(rng, y.shape, noise_var)
-    return dict(rx=y.astype(np.complex64), pilots=pilots, bits=bits, x=x, h=h,
+        y += awgn(rng, y.shape, noise_var)
+    return dict(rx=np.ascontiguousarray(y), pilots=pilots, bits=bits, x=x, h=h,
                 noise_var=float(noise_var))
 
 
 def make_batch(name: str, n_slots: Optional[int] = None, snr_db: Optional[Sequence[float]] = None,
-               keep_truth: bool = True, first_slot: int = 0):
+               keep_truth: bool = True, first_slot: int = 0, workers: int = 1):
     """Draw a batch of slots for a named workload.
 
-    Slot i is drawn at SNR point i mod len(snr_grid), realisation i div len(snr_grid),
-    each from its own seeded stream.  Returns stacked arrays with a leading slot axis.
+    Slot i is drawn at SNR point i mod len(snr_grid), realisation first_slot + i div
+    len(snr_grid), each from its own seeded stream, so the result does not depend on
+    ``workers`` (threads drawing slots concurrently).  Returns stacked arrays with a
+    leading slot axis.
     """
     cfg = CONFIGS[name]
     grid = tuple(snr_db) if snr_db is not None else cfg["snr_db"]
@@ -295,18 +299,28 @@ def make_batch(name: str, n_slots: Optional[int] = None, snr_db: Optional[Sequen
     rx = np.empty((n, shape.n_symb, shape.n_sc, shape.n_rx), np.complex64)
     pil = np.empty((n, shape.n_occ, shape.dmrs_td, shape.n_pilot, shape.n_layers), np.complex64)
     nv = np.empty(n, np.float32)
-    bits, xs, hs, snrs = [], [], [], []
-    for i in range(n):
+    snrs = np.array([grid[i % len(grid)] for i in range(n)])
+    truth = [None] * n
+
+    def one(i):
         si = i % len(grid)
         sl = first_slot + i // len(grid)
         snr_index = cfg["snr_db"].index(grid[si]) if grid[si] in cfg["snr_db"] else 100 + si
         rng = rng_for(cfg["config_id"], snr_index, sl)
         d = make_slot(shape, rng, cfg["scs_hz"], cfg["pdp"], grid[si])
         rx[i], pil[i], nv[i] = d["rx"], d["pilots"], d["noise_var"]
-        snrs.append(grid[si])
         if keep_truth:
-            bits.append(d["bits"]); xs.append(d["x"]); hs.append(d["h"])
-    out = dict(shape=shape, rx=rx, pilots=pil, noise_var=nv, snr_db=np.array(snrs))
+            truth[i] = (d["bits"], d["x"], d["h"])
+
+    if workers > 1:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(n)))
+    else:
+        for i in range(n):
+            one(i)
+    out = dict(shape=shape, rx=rx, pilots=pil, noise_var=nv, snr_db=snrs)
     if keep_truth:
-        out.update(bits=np.stack(bits), x=np.stack(xs), h=np.stack(hs))
+        out.update(bits=np.stack([t[0] for t in truth]), x=np.stack([t[1] for t in truth]),
+                   h=np.stack([t[2] for t in truth]))
     return out

@@ -1,0 +1,136 @@
+"""The C ABI on the host (no GPU): the library loads, exports what the header declares,
+and its validation rejects bad input before any launch."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2510_07843_amd as ranphy
+import synth
+from synth import SlotShape
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ranphy.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ranphy.LIB_PATH):
+        from paper_2510_07843_amd import build
+        build.build_library()
+    return ranphy.lib()
+
+
+def header_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"RANPHY_API\s+[\w\s\*]+?\b(ranphy_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    assert header_functions() == sorted(ranphy.EXPORTED_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", ranphy.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s+(\w+)$", out, re.M))
+    for f in header_functions():
+        assert f in exported
+        assert hasattr(L, f)
+    # Only the C ABI is visible.
+    assert exported == set(header_functions())
+
+
+def test_abi_version_matches_header(L):
+    v = int(re.search(r"#define RANPHY_ABI_VERSION (\d+)", open(HEADER).read()).group(1))
+    assert ranphy.abi_version() == v
+
+
+def test_status_strings(L):
+    for s in (0, -1, -2, -3, 7):
+        assert isinstance(ranphy.status_str(s), str) and ranphy.status_str(s)
+    assert ranphy.status_str(-2) != ranphy.status_str(-1)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "m"])
+def test_buffer_sizes_match_layouts(L, name):
+    sh = synth.CONFIGS[name]["shape"].with_slots(3)
+    S, J = 3, sh.n_pilot
+    assert ranphy.buffer_floats(sh, ranphy.BUF_RX) == 2 * S * 14 * sh.n_sc * sh.n_rx
+    assert ranphy.buffer_floats(sh, ranphy.BUF_PILOTS) == 2 * S * sh.n_occ * sh.dmrs_td * J * sh.n_layers
+    assert ranphy.buffer_floats(sh, ranphy.BUF_H, ranphy.H_PILOT) == 2 * S * sh.n_occ * J * sh.n_rx * sh.n_layers
+    assert ranphy.buffer_floats(sh, ranphy.BUF_H, ranphy.H_FULL) == 2 * S * sh.n_occ * sh.n_sc * sh.n_rx * sh.n_layers
+    assert ranphy.buffer_floats(sh, ranphy.BUF_NOISE_VAR) == S
+    assert ranphy.buffer_floats(sh, ranphy.BUF_X) == 2 * S * sh.n_dsym * sh.n_sc * sh.n_layers
+    assert ranphy.buffer_floats(sh, ranphy.BUF_NV) == S * sh.n_dsym * sh.n_sc * sh.n_layers
+    assert ranphy.buffer_floats(sh, ranphy.BUF_LLR) == S * sh.n_dsym * sh.n_sc * sh.n_layers * sh.qm
+
+
+GOOD = dict(n_prb=4, n_symb=14, n_rx=8, n_layers=4, qm=4, dmrs_comb=4, dmrs_td=1, dmrs_sym0=(2,),
+            n_slots=2)
+
+BAD = [
+    (dict(n_prb=0), -1), (dict(n_prb=276), -1), (dict(n_symb=15), -1), (dict(n_symb=0), -1),
+    (dict(n_rx=0), -1), (dict(n_rx=65, n_layers=4), -2), (dict(n_layers=0), -1),
+    (dict(n_layers=17, n_rx=32, dmrs_comb=8, dmrs_td=2), -2), (dict(n_layers=9, n_rx=8), -2),
+    (dict(qm=3), -1), (dict(qm=10), -1), (dict(dmrs_comb=3), -1), (dict(dmrs_comb=1), -1),
+    (dict(dmrs_td=3), -1), (dict(n_layers=5), -2),  # 5 > C T = 4
+    (dict(dmrs_sym0=(13,), dmrs_td=2), -1), (dict(dmrs_sym0=(-1,)), -1),
+    (dict(dmrs_sym0=(5, 3)), -1), (dict(dmrs_sym0=(2, 2)), -1), (dict(dmrs_sym0=(2, 3), dmrs_td=2), -1),
+    (dict(n_slots=-1), -1), (dict(dmrs_sym0=(0,), n_symb=1), -1),  # no data symbol left
+]
+
+
+def _desc(**kw):
+    a = dict(GOOD)
+    a.update(kw)
+    return ranphy.SlotDesc.make(**a)
+
+
+def _calls(L, d, p):
+    P = ctypes.c_void_p
+    return [
+        L.ranphy_chest_ls(ctypes.byref(d), P(p), P(p), P(p), 0, None),
+        L.ranphy_mmse_detect(ctypes.byref(d), P(p), P(p), 0, P(p), P(p), P(p), None),
+        L.ranphy_llr_demap(ctypes.byref(d), P(p), P(p), P(p), None),
+    ]
+
+
+@pytest.mark.parametrize("kw,code", BAD)
+def test_invalid_descriptors_rejected_before_launch(L, kw, code):
+    d = _desc(**kw)
+    # Pointers that would fault if touched; validation must stop first.
+    assert _calls(L, d, 0x1000) == [code] * 3
+    assert L.ranphy_buffer_floats(ctypes.byref(d), ranphy.BUF_RX, 0) == code
+
+
+def test_null_descriptor(L):
+    P = ctypes.c_void_p
+    assert L.ranphy_chest_ls(None, P(0x1000), P(0x1000), P(0x1000), 0, None) == -1
+    assert L.ranphy_mmse_detect(None, P(8), P(8), 0, P(8), P(8), P(8), None) == -1
+    assert L.ranphy_llr_demap(None, P(8), P(8), P(8), None) == -1
+
+
+def test_null_and_misaligned_pointers_rejected(L):
+    d = _desc()
+    assert _calls(L, d, 0) == [-1] * 3
+    assert _calls(L, d, 0x1004) == [-1] * 3
+    P = ctypes.c_void_p
+    assert L.ranphy_chest_ls(ctypes.byref(d), P(8), P(8), P(8), 2, None) == -1  # bad h_res
+    assert L.ranphy_mmse_detect(ctypes.byref(d), P(8), P(8), 5, P(8), P(8), P(8), None) == -1
+
+
+def test_empty_batch_is_a_no_op(L):
+    d = _desc(n_slots=0)
+    assert _calls(L, d, 0) == [0] * 3
+
+
+def test_binding_refuses_host_tensors(L):
+    import torch
+    sh = SlotShape(**{k: v for k, v in GOOD.items()})
+    rx = torch.zeros(ranphy.buffer_floats(sh, ranphy.BUF_RX) // 2, dtype=torch.complex64)
+    pil = torch.zeros(ranphy.buffer_floats(sh, ranphy.BUF_PILOTS) // 2, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        ranphy.chest_ls(sh, rx, pil, h=torch.zeros(1, dtype=torch.complex64))
