@@ -150,6 +150,12 @@ SHAPES = {
     "prb9_l12_2occ": SlotShape(9, 14, 40, 12, 4, 8, 2, (2, 10), 1),
     "prb13_l16_r17": SlotShape(13, 14, 17, 16, 2, 8, 2, (3,), 1),
     "prb4_short": SlotShape(4, 7, 4, 2, 4, 2, 1, (0,), 2),
+    # matrix-core detector shapes (one occasion, 5..16 layers, Nr a multiple of 16)
+    "prb5_l9_r32": SlotShape(5, 14, 32, 9, 4, 8, 2, (2,), 2),
+    "prb3_l12_r48": SlotShape(3, 14, 48, 12, 6, 8, 2, (3,), 2),
+    "prb2_l5_r16": SlotShape(2, 14, 16, 5, 2, 4, 2, (2,), 3),
+    "prb4_l8_short": SlotShape(4, 7, 16, 8, 4, 4, 2, (0,), 2),
+    "prb1_l16_dmrs_end": SlotShape(1, 14, 64, 16, 8, 8, 2, (12,), 2),
 }
 
 
