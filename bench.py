@@ -86,7 +86,19 @@ def main():
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
+    if args.copy_ref:
+        import torch
+        n = args.copy_ref * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes_each_way": n * 4, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (see the "
                                    "sharding design: slots, cells and UEs are independent)"}))

@@ -38,6 +38,7 @@ namespace {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr float kPivotRel = 16.f * FLT_EPSILON;
+constexpr int kXcds = 8;
 
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -59,31 +60,35 @@ __device__ __forceinline__ float uniform_read(float v, int lane) {
 }
 
 // One Gauss-Jordan step on pivot K.  Lane (q, c) holds A[4q+v][c] in (ar[v], ai[v]).
+//   pivot row:     A[K][j]  <- A[K][j] / p
+//   pivot column:  A[i][K]  <- -A[i][K] / p
+//   pivot:         A[K][K]  <- 1 / p
+//   elsewhere:     A[i][j]  <- A[i][j] - A[i][K] A[K][j] / p
 template <int K>
 __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int q, int c, int nl,
                                         float tiny, bool& ok) {
   constexpr int KV = K & 3;
-  constexpr int KL = 16 * (K >> 2) + K;
-  const float p = uniform_read(ar[KV], KL);
+  constexpr int KQ = K >> 2;
+  const float p = uniform_read(ar[KV], 16 * KQ + K);
   ok = ok && (K >= nl || p > tiny);  // padded layers carry an identity block
-  const float pinv = 1.f / p;
+  const float pinv = __builtin_amdgcn_rcpf(p);
   // Row K at this lane's column c (held by lane (K/4, c), register K%4), scaled.
-  const float rr = lane_read(ar[KV], 16 * (K >> 2) + c) * pinv;
-  const float ri = lane_read(ai[KV], 16 * (K >> 2) + c) * pinv;
+  const int src = 16 * KQ + c;
+  const float rr = lane_read(ar[KV], src) * pinv;
+  const float ri = lane_read(ai[KV], src) * pinv;
   const bool col_k = (c == K);
+  const bool q_k = (q == KQ);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const float cr = row_bcast<K>(ar[v]);  // A[4q+v][K]
     const float ci = row_bcast<K>(ai[v]);
-    const bool row_k = (4 * q + v == K);
-    // Generic entry: A - A[i][K] A[K][j] / p.
-    float nr = ar[v] - (cr * rr - ci * ri);
-    float ni = ai[v] - (cr * ri + ci * rr);
+    float nr = fmaf(-cr, rr, fmaf(ci, ri, ar[v]));
+    float ni = fmaf(-cr, ri, fmaf(-ci, rr, ai[v]));
     if (col_k) {
       nr = -cr * pinv;
       ni = -ci * pinv;
     }
-    if (row_k) {
+    if (v == KV && q_k) {  // pivot row (4q + v == K only for v == K % 4)
       nr = col_k ? pinv : rr;
       ni = col_k ? 0.f : ri;
     }
@@ -101,7 +106,7 @@ __device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], int q, in
   }
 }
 
-template <int HRES>
+template <int HRES, int NL>
 __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
                                                         const float* __restrict__ nvar,
@@ -112,51 +117,49 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4;  // K group / accumulator row group
   const int c = lane & 15;  // layer (A/B operands), column (accumulators)
-  const int NR = g.n_rx, NL = g.n_layers, ND = g.n_dsym;
+  const int NR = g.n_rx, ND = g.n_dsym;
 
+  // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run of
+  // subcarriers so that its L2 reads every pilot of the run once.
   const int64_t total = (int64_t)g.n_slots * g.n_sc;
-  int64_t sid = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t per_xcd = gridDim.x / kXcds;
+  const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  int64_t sid = blk * 4 + wave;
   const bool live = sid < total;
   if (!live) sid = total - 1;  // dead waves mirror the last subcarrier and store nothing
   const int64_t slot = sid / g.n_sc;
   const int k = (int)(sid % g.n_sc);
+  const bool qv = 16 * q < NR;  // this lane group's antennas exist
 
   // ---- 1. channel in registers: lane (q, p = c), step s: antenna 16 q + s ----------------
   float hr[16], hi[16];
-  {
+  if (c < NL && qv) {
     const int p = c;
-    const bool pv = p < NL;
-    const float2* __restrict__ b0;
-    const float2* __restrict__ b1;
-    float a = 0.f;
     if (HRES == 0) {
-      int j0 = 0, j1 = 0;
-      if (pv) freq_rule(g, p, k, j0, j1, a);
-      const int64_t base = slot * g.n_pilot;  // one occasion
-      b0 = h + (base + j0) * NR * NL;
-      b1 = h + (base + j1) * NR * NL;
-    } else {
-      b0 = h + (slot * g.n_sc + k) * NR * NL;
-      b1 = b0;
-    }
+      int j0, j1;
+      float a;
+      freq_rule(g, p, k, j0, j1, a);
+      const float2* __restrict__ b0 = h + ((slot * g.n_pilot + j0) * NR + 16 * q) * NL + p;
+      const float2* __restrict__ b1 = h + ((slot * g.n_pilot + j1) * NR + 16 * q) * NL + p;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int r = 16 * q + s;
-      float vr = 0.f, vi = 0.f;
-      if (pv && r < NR) {
-        const float2 v0 = b0[r * NL + p];
-        if (HRES == 0) {
-          const float2 v1 = b1[r * NL + p];
-          vr = v0.x + a * (v1.x - v0.x);
-          vi = v0.y + a * (v1.y - v0.y);
-        } else {
-          vr = v0.x;
-          vi = v0.y;
-        }
+      for (int s = 0; s < 16; ++s) {
+        const float2 v0 = b0[s * NL];
+        const float2 v1 = b1[s * NL];
+        hr[s] = v0.x + a * (v1.x - v0.x);
+        hi[s] = v0.y + a * (v1.y - v0.y);
       }
-      hr[s] = vr;
-      hi[s] = vi;
+    } else {
+      const float2* __restrict__ b0 = h + ((slot * g.n_sc + k) * NR + 16 * q) * NL + p;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        const float2 v0 = b0[s * NL];
+        hr[s] = v0.x;
+        hi[s] = v0.y;
+      }
     }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) hr[s] = hi[s] = 0.f;
   }
 
   // ---- 2. received samples: lane (q, d = c), antennas 16 q .. 16 q + 15 (128 B) ----------
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
     const int d = c;
     // One occasion: data symbols are those before and after its T DMRS symbols.
     const int s = (d < g.sym0[0]) ? d : d + g.td;
-    if (d < ND && 16 * q < NR) {
+    if (d < ND && qv) {
       const float4* __restrict__ src = reinterpret_cast<const float4*>(
           rx + ((slot * g.n_symb + s) * g.n_sc + k) * NR + 16 * q);
 #pragma unroll
@@ -183,17 +186,18 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   }
 
   // ---- 3. Gram and matched filter on the matrix cores -------------------------------------
-  floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, acc_zr = acc_g, acc_za = acc_g,
-          acc_zb = acc_g;
+  // Z = H^H Y with three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
+  //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
+  floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, acc_m1 = acc_g, acc_m2 = acc_g,
+          acc_m3 = acc_g;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     acc_g = mfma(hr[s], hr[s], acc_g);
     acc_g = mfma(hi[s], hi[s], acc_g);
     acc_p = mfma(hr[s], hi[s], acc_p);
-    acc_zr = mfma(hr[s], yr[s], acc_zr);
-    acc_zr = mfma(hi[s], yi[s], acc_zr);
-    acc_za = mfma(hr[s], yi[s], acc_za);
-    acc_zb = mfma(hi[s], yr[s], acc_zb);
+    acc_m1 = mfma(hr[s], yr[s], acc_m1);
+    acc_m2 = mfma(hi[s], yi[s], acc_m2);
+    acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
   }
 
   // ---- 4. G = Re + j (P - P^T) + s2 I, padded layers -> identity; invert in place ---------
@@ -227,15 +231,21 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   // ---- 5. X_hat = G^-1 Z on the matrix cores ---------------------------------------------
   // A[i = c][m = 4q + s] = G^-1[c][4q+s] = conj(G^-1[4q+s][c]) = (ar[s], -ai[s]);
   // B[m = 4q + s][d = c] = Z[4q+s][c].
-  floatx4 acc_xr = {0.f, 0.f, 0.f, 0.f}, acc_xi = acc_xr;
+  // Three real products again: Re = ar zr + ai zi,  Im = (ar - ai)(zr + zi) - ar zr + ai zi.
+  floatx4 acc_n1 = {0.f, 0.f, 0.f, 0.f}, acc_n2 = acc_n1, acc_n3 = acc_n1;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const float zr = acc_zr[s];
-    const float zi = acc_za[s] - acc_zb[s];
-    acc_xr = mfma(ar[s], zr, acc_xr);
-    acc_xr = mfma(ai[s], zi, acc_xr);
-    acc_xi = mfma(ar[s], zi, acc_xi);
-    acc_xi = mfma(-ai[s], zr, acc_xi);
+    const float zr = acc_m1[s] + acc_m2[s];
+    const float zi = acc_m3[s] - acc_m1[s] + acc_m2[s];
+    acc_n1 = mfma(ar[s], zr, acc_n1);
+    acc_n2 = mfma(ai[s], zi, acc_n2);
+    acc_n3 = mfma(ar[s] - ai[s], zr + zi, acc_n3);
+  }
+  floatx4 acc_xr, acc_xi;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    acc_xr[v] = acc_n1[v] + acc_n2[v];
+    acc_xi[v] = acc_n3[v] - acc_n1[v] + acc_n2[v];
   }
 
   // ---- 6. unbias and store: lane (q, d = c) holds layers 4q .. 4q+3 of data symbol d ------
@@ -250,7 +260,7 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
       const int l = 4 * q + v;
       if (l < NL) {
         const float sd = s2 * dl[v];
-        const float im = 1.f / (1.f - sd);
+        const float im = __builtin_amdgcn_rcpf(1.f - sd);
         if (ok) {
           x[o + l] = make_float2(acc_xr[v] * im, acc_xi[v] * im);
           nv[o + l] = sd * im;
@@ -263,22 +273,46 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   }
 }
 
+template <int HRES, int NL>
+void launch_one(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
+                float2* x, float* nv, hipStream_t s) {
+  hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL>), grid, dim3(256), 0, s, g, rx, h, nvar, x, nv);
+}
+
+template <int HRES>
+void launch_nl(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
+               float2* x, float* nv, hipStream_t s) {
+  switch (g.n_layers) {
+    case 5: launch_one<HRES, 5>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 6: launch_one<HRES, 6>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 7: launch_one<HRES, 7>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 8: launch_one<HRES, 8>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 9: launch_one<HRES, 9>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 10: launch_one<HRES, 10>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 11: launch_one<HRES, 11>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 12: launch_one<HRES, 12>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 13: launch_one<HRES, 13>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 14: launch_one<HRES, 14>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 15: launch_one<HRES, 15>(g, grid, rx, h, nvar, x, nv, s); break;
+    default: launch_one<HRES, 16>(g, grid, rx, h, nvar, x, nv, s); break;
+  }
+}
+
 }  // namespace
 
 bool mmse_mfma_eligible(const Geom& g, const void* rx) {
   // 16-byte aligned received grid: each lane reads its antennas with 16-byte loads.
-  return ((uintptr_t)rx & 15u) == 0 && g.n_occ == 1 && g.n_layers >= 5 && g.n_layers <= 16 && g.n_rx % 16 == 0 &&
-         g.n_rx <= 64 && g.n_dsym <= 16;
+  return ((uintptr_t)rx & 15u) == 0 && g.n_occ == 1 && g.n_layers >= 5 && g.n_layers <= 16 &&
+         g.n_rx % 16 == 0 && g.n_rx <= 64 && g.n_dsym <= 16;
 }
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
                             const float* nvar, float2* x, float* nv, hipStream_t s) {
   const int64_t waves = (int64_t)g.n_slots * g.n_sc;
-  const dim3 block(256), grid((unsigned)((waves + 3) / 4));
-  if (h_res == 0)
-    hipLaunchKernelGGL(mmse_mfma_kernel<0>, grid, block, 0, s, g, rx, h, nvar, x, nv);
-  else
-    hipLaunchKernelGGL(mmse_mfma_kernel<1>, grid, block, 0, s, g, rx, h, nvar, x, nv);
+  const int64_t blocks = (waves + 3) / 4;
+  const dim3 grid((unsigned)((blocks + kXcds - 1) / kXcds * kXcds));
+  if (h_res == 0) launch_nl<0>(g, grid, rx, h, nvar, x, nv, s);
+  else launch_nl<1>(g, grid, rx, h, nvar, x, nv, s);
   return hipGetLastError();
 }
 
