@@ -24,6 +24,7 @@ struct Geom {
   int n_layers;
   int qm;
   int comb;     // C
+  int comb_log2;
   int td;       // T
   int n_occ;
   int n_pilot;  // ceil(n_sc / C)
@@ -40,9 +41,9 @@ struct Geom {
 // pilots at k = c + C j (c = p mod C), nearest pilot held outside the first and last one.
 __device__ __forceinline__ void freq_rule(const Geom& g, int p, int k, int& j0, int& j1,
                                           float& a) {
-  const int C = g.comb;
+  const int C = g.comb, L = g.comb_log2;  // C is a power of two
   const int c = p & (C - 1);
-  const int jp = (g.n_sc - c + C - 1) / C;
+  const int jp = (g.n_sc - c + C - 1) >> L;
   const int last = c + C * (jp - 1);
   if (k <= c) {
     j0 = j1 = 0;
@@ -51,9 +52,9 @@ __device__ __forceinline__ void freq_rule(const Geom& g, int p, int k, int& j0, 
     j0 = j1 = jp - 1;
     a = 0.f;
   } else {
-    j0 = (k - c) / C;
+    j0 = (k - c) >> L;
     j1 = j0 + 1;
-    a = (float)(k - c - C * j0) / (float)C;
+    a = (float)(k - c - C * j0) * (1.f / (float)C);
   }
 }
 

@@ -44,11 +44,23 @@ __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Value of lane (16 * (lane / 16) + src) within each row of 16 lanes.
+// Value of lane SRC of each row of 16 lanes (DPP row_newbcast; a VALU move, no LDS trip).
 template <int SRC>
 __device__ __forceinline__ float row_bcast(float v) {
-  constexpr int pattern = 0x10 | (SRC << 5);  // bit mode: and 0x10, or SRC
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), pattern));
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + SRC, 0xF, 0xF, false));
+}
+
+// Value held by row group G (lanes 16 G .. 16 G + 15) at the same position in the row, for
+// every row group: permlane16_swap(x, x) yields rows (x0,x0,x2,x2) and (x1,x1,x3,x3);
+// permlane32_swap(e, e) of e = (a,a,b,b) yields (a,a,a,a) and (b,b,b,b).
+template <int G>
+__device__ __forceinline__ float group_bcast(float v) {
+  const int x = __float_as_int(v);
+  const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  const int e = (G & 1) ? p[1] : p[0];
+  const auto r = __builtin_amdgcn_permlane32_swap(e, e, false, false);
+  return __int_as_float((G & 2) ? r[1] : r[0]);
 }
 
 __device__ __forceinline__ float lane_read(float v, int src_lane) {
@@ -59,38 +71,42 @@ __device__ __forceinline__ float uniform_read(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// One Gauss-Jordan step on pivot K.  Lane (q, c) holds A[4q+v][c] in (ar[v], ai[v]).
-//   pivot row:     A[K][j]  <- A[K][j] / p
-//   pivot column:  A[i][K]  <- -A[i][K] / p
-//   pivot:         A[K][K]  <- 1 / p
-//   elsewhere:     A[i][j]  <- A[i][j] - A[i][K] A[K][j] / p
+// One Gauss-Jordan step on pivot K, with the pivot-column scaling deferred.  Lane (q, c)
+// holds R[4q+v][c] in (ar[v], ai[v]); the matrix of the textbook in-place elimination is
+// A[i][j] = R[i][j] s_j, where s_j = 1 until column j has been the pivot column and
+// s_j = -1/p_j afterwards.  One step on the stored values:
+//   pivot row:     R[K][j]  <- R[K][j] / p      (j != K),   R[K][K] <- -1
+//   pivot column:  unchanged (its scale becomes s_K = -1/p)
+//   elsewhere:     R[i][j]  <- R[i][j] - R[i][K] R[K][j] / p
+// Every other update is linear in each column, so a uniform column scale commutes with it.
+// Each lane keeps s_c of its own column c in `scale`.
 template <int K>
-__device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int q, int c, int nl,
-                                        float tiny, bool& ok) {
+__device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& scale, int q,
+                                        int c, int nl, const float (&gd)[16], bool& ok) {
   constexpr int KV = K & 3;
   constexpr int KQ = K >> 2;
   const float p = uniform_read(ar[KV], 16 * KQ + K);
-  ok = ok && (K >= nl || p > tiny);  // padded layers carry an identity block
+  // A pivot that is not positive relative to its original diagonal entry means the matrix
+  // is not numerically positive definite; padded layers carry an identity block.
+  ok = ok && (K >= nl || p > kPivotRel * gd[K]);
   const float pinv = __builtin_amdgcn_rcpf(p);
-  // Row K at this lane's column c (held by lane (K/4, c), register K%4), scaled.
-  const int src = 16 * KQ + c;
-  const float rr = lane_read(ar[KV], src) * pinv;
-  const float ri = lane_read(ai[KV], src) * pinv;
+  // Row K at this lane's column c (row group K/4, register K%4), scaled; zero in the pivot
+  // column so that the rank-1 update leaves that column untouched.
   const bool col_k = (c == K);
-  const bool q_k = (q == KQ);
+  const float rw = group_bcast<KQ>(ar[KV]);
+  const float iw = group_bcast<KQ>(ai[KV]);
+  const float rr = col_k ? 0.f : rw * pinv;
+  const float ri = col_k ? 0.f : iw * pinv;
+  scale = col_k ? -pinv : scale;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const float cr = row_bcast<K>(ar[v]);  // A[4q+v][K]
+    const float cr = row_bcast<K>(ar[v]);  // R[4q+v][K]
     const float ci = row_bcast<K>(ai[v]);
     float nr = fmaf(-cr, rr, fmaf(ci, ri, ar[v]));
     float ni = fmaf(-cr, ri, fmaf(-ci, rr, ai[v]));
-    if (col_k) {
-      nr = -cr * pinv;
-      ni = -ci * pinv;
-    }
-    if (v == KV && q_k) {  // pivot row (4q + v == K only for v == K % 4)
-      nr = col_k ? pinv : rr;
-      ni = col_k ? 0.f : ri;
+    if (v == KV && q == KQ) {  // pivot row (4q + v == K only for v == K % 4)
+      nr = col_k ? -1.f : rr;
+      ni = ri;
     }
     ar[v] = nr;
     ai[v] = ni;
@@ -98,11 +114,19 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], int q, i
 }
 
 template <int K>
-__device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], int q, int c, int nl,
-                                       float tiny, bool& ok) {
+__device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], float& scale, int q,
+                                       int c, int nl, const float (&gd)[16], bool& ok) {
   if constexpr (K < 16) {
-    gj_step<K>(ar, ai, q, c, nl, tiny, ok);
-    gj_all<K + 1>(ar, ai, q, c, nl, tiny, ok);
+    gj_step<K>(ar, ai, scale, q, c, nl, gd, ok);
+    gj_all<K + 1>(ar, ai, scale, q, c, nl, gd, ok);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16]) {
+  if constexpr (K < 16) {
+    gd[K] = uniform_read(ar[K & 3], 16 * (K >> 2) + K);
+    read_diag<K + 1>(ar, gd);
   }
 }
 
@@ -120,69 +144,77 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   const int NR = g.n_rx, ND = g.n_dsym;
 
   // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a contiguous run of
-  // subcarriers so that its L2 reads every pilot of the run once.
-  const int64_t total = (int64_t)g.n_slots * g.n_sc;
-  const int64_t per_xcd = gridDim.x / kXcds;
-  const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  int64_t sid = blk * 4 + wave;
+  // subcarriers so that its L2 reads every pilot of the run once.  All per-wave indices are
+  // wave-uniform (kept in scalar registers).
+  const int total = g.n_slots * g.n_sc;
+  const int per_xcd = gridDim.x / kXcds;
+  const int blk = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  int sid = __builtin_amdgcn_readfirstlane(blk * 4 + wave);
   const bool live = sid < total;
   if (!live) sid = total - 1;  // dead waves mirror the last subcarrier and store nothing
-  const int64_t slot = sid / g.n_sc;
-  const int k = (int)(sid % g.n_sc);
-  const bool qv = 16 * q < NR;  // this lane group's antennas exist
+  const int slot = __builtin_amdgcn_readfirstlane(sid / g.n_sc);
+  const int k = __builtin_amdgcn_readfirstlane(sid - slot * g.n_sc);
+  const int nq = NR >> 4;       // lane groups that carry antennas
+  const bool qv = q < nq;
+  const int qc = qv ? q : nq - 1;  // clamped: every address below is in bounds
 
-  // ---- 1. channel in registers: lane (q, p = c), step s: antenna 16 q + s ----------------
-  float hr[16], hi[16];
-  if (c < NL && qv) {
-    const int p = c;
-    if (HRES == 0) {
-      int j0, j1;
-      float a;
-      freq_rule(g, p, k, j0, j1, a);
-      const float2* __restrict__ b0 = h + ((slot * g.n_pilot + j0) * NR + 16 * q) * NL + p;
-      const float2* __restrict__ b1 = h + ((slot * g.n_pilot + j1) * NR + 16 * q) * NL + p;
+  // ---- 1./2. issue every load of this subcarrier before using any of them ----------------
+  // Channel, lane (q, p = c), step s: antenna 16 q + s.  Layers past NL read layer NL-1; the
+  // Gram rows and columns they produce are replaced by an identity block below.
+  const int pc = c < NL ? c : NL - 1;
+  float2 h0[16], h1[16];
+  float a = 0.f;
+  if (HRES == 0) {
+    int j0, j1;
+    freq_rule(g, pc, k, j0, j1, a);
+    const float2* __restrict__ b0 = h + ((int64_t)(slot * g.n_pilot + j0) * NR + 16 * qc) * NL + pc;
+    const float2* __restrict__ b1 = h + ((int64_t)(slot * g.n_pilot + j1) * NR + 16 * qc) * NL + pc;
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const float2 v0 = b0[s * NL];
-        const float2 v1 = b1[s * NL];
-        hr[s] = v0.x + a * (v1.x - v0.x);
-        hi[s] = v0.y + a * (v1.y - v0.y);
-      }
-    } else {
-      const float2* __restrict__ b0 = h + ((slot * g.n_sc + k) * NR + 16 * q) * NL + p;
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        const float2 v0 = b0[s * NL];
-        hr[s] = v0.x;
-        hi[s] = v0.y;
-      }
+    for (int s = 0; s < 16; ++s) {
+      h0[s] = b0[s * NL];
+      h1[s] = b1[s * NL];
     }
   } else {
+    const float2* __restrict__ b0 = h + ((int64_t)(slot * g.n_sc + k) * NR + 16 * qc) * NL + pc;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) h0[s] = b0[s * NL];
+  }
+  // Received samples, lane (q, d = c): antennas 16 q .. 16 q + 15 of data symbol d (128 B).
+  // Symbols past ND read symbol ND-1; their Z columns are never stored.
+  float4 yv[8];
+  {
+    const int d = c < ND ? c : ND - 1;
+    const int s = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(
+        rx + ((int64_t)(slot * g.n_symb + s) * g.n_sc + k) * NR + 16 * qc);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) yv[i] = src[i];
+  }
+  const float s2 = nvar[slot];
+  // Keep all loads of this subcarrier in flight together: one memory latency per wave.
+  __builtin_amdgcn_sched_barrier(0);
+
+  float hr[16], hi[16], yr[16], yi[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    if (HRES == 0) {
+      hr[s] = fmaf(a, h1[s].x - h0[s].x, h0[s].x);
+      hi[s] = fmaf(a, h1[s].y - h0[s].y, h0[s].y);
+    } else {
+      hr[s] = h0[s].x;
+      hi[s] = h0[s].y;
+    }
+  }
+  if (!qv) {  // antenna groups past NR contribute nothing
 #pragma unroll
     for (int s = 0; s < 16; ++s) hr[s] = hi[s] = 0.f;
   }
-
-  // ---- 2. received samples: lane (q, d = c), antennas 16 q .. 16 q + 15 (128 B) ----------
-  float yr[16], yi[16];
-  {
-    const int d = c;
-    // One occasion: data symbols are those before and after its T DMRS symbols.
-    const int s = (d < g.sym0[0]) ? d : d + g.td;
-    if (d < ND && qv) {
-      const float4* __restrict__ src = reinterpret_cast<const float4*>(
-          rx + ((slot * g.n_symb + s) * g.n_sc + k) * NR + 16 * q);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float4 v = src[i];
-        yr[2 * i] = v.x;
-        yi[2 * i] = v.y;
-        yr[2 * i + 1] = v.z;
-        yi[2 * i + 1] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) yr[i] = yi[i] = 0.f;
-    }
+  for (int i = 0; i < 8; ++i) {
+    yr[2 * i] = yv[i].x;
+    yi[2 * i] = yv[i].y;
+    yr[2 * i + 1] = yv[i].z;
+    yi[2 * i + 1] = yv[i].w;
   }
 
   // ---- 3. Gram and matched filter on the matrix cores -------------------------------------
@@ -204,8 +236,10 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   float* __restrict__ tp = lds_t[wave];
 #pragma unroll
   for (int v = 0; v < 4; ++v) tp[(4 * q + v) * 17 + c] = acc_p[v];
-  __syncthreads();
-  const float s2 = nvar[slot];
+  // Only this wave reads what it wrote: order the LDS accesses within the wave.
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   float ar[4], ai[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -214,19 +248,17 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
     ar[v] = in ? acc_g[v] + ((i == c) ? s2 : 0.f) : ((i == c) ? 1.f : 0.f);
     ai[v] = in ? acc_p[v] - tp[c * 17 + i] : 0.f;
   }
-  // Pivot threshold relative to the largest diagonal entry.
-  float dmax = 0.f;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) dmax = fmaxf(dmax, (4 * q + v == c) ? ar[v] : 0.f);
-  dmax = fmaxf(dmax, __shfl_xor(dmax, 1));
-  dmax = fmaxf(dmax, __shfl_xor(dmax, 2));
-  dmax = fmaxf(dmax, __shfl_xor(dmax, 4));
-  dmax = fmaxf(dmax, __shfl_xor(dmax, 8));
-  dmax = fmaxf(dmax, __shfl_xor(dmax, 16));
-  dmax = fmaxf(dmax, __shfl_xor(dmax, 32));
-  const float tiny = kPivotRel * uniform_read(dmax, 0);
+  float gd[16];
+  read_diag<0>(ar, gd);
   bool ok = true;
-  gj_all<0>(ar, ai, q, c, NL, tiny, ok);
+  float scale = 1.f;
+  gj_all<0>(ar, ai, scale, q, c, NL, gd, ok);
+  // Apply the deferred column scales: lane (q, c) now holds G^-1[4q+v][c].
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    ar[v] *= scale;
+    ai[v] *= scale;
+  }
 
   // ---- 5. X_hat = G^-1 Z on the matrix cores ---------------------------------------------
   // A[i = c][m = 4q + s] = G^-1[c][4q+s] = conj(G^-1[4q+s][c]) = (ar[s], -ai[s]);
@@ -254,7 +286,7 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
   const int d = c;
   if (live && d < ND) {
-    const int64_t o = ((slot * ND + d) * g.n_sc + k) * NL;
+    const int64_t o = ((int64_t)(slot * ND + d) * g.n_sc + k) * NL;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int l = 4 * q + v;

@@ -44,6 +44,7 @@ int make_geom(const ranphy_slot_desc* d, Geom* g) {
   z.n_layers = d->n_layers;
   z.qm = d->qm;
   z.comb = d->dmrs_comb;
+  z.comb_log2 = d->dmrs_comb == 2 ? 1 : (d->dmrs_comb == 4 ? 2 : 3);
   z.td = d->dmrs_td;
   z.n_occ = d->n_occ;
   z.n_pilot = (z.n_sc + z.comb - 1) / z.comb;
