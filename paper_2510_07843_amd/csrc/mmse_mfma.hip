@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
                                                         float2* __restrict__ x,
                                                         float* __restrict__ nv) {
   __shared__ float lds_t[4][16 * 17];
+  __shared__ __attribute__((aligned(16))) float2 lds_h[4 * kMaxRx * NL];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4;  // K group / accumulator row group
@@ -148,36 +149,62 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   // wave-uniform (kept in scalar registers).
   const int total = g.n_slots * g.n_sc;
   const int per_xcd = gridDim.x / kXcds;
-  const int blk = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
-  int sid = __builtin_amdgcn_readfirstlane(blk * 4 + wave);
-  const bool live = sid < total;
-  if (!live) sid = total - 1;  // dead waves mirror the last subcarrier and store nothing
+  int blk = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  const bool live = blk * 4 < total;  // total is a multiple of 4 (12 subcarriers per PRB)
+  if (!live) blk = total / 4 - 1;     // dead blocks mirror the last block and store nothing
+  const int sid = __builtin_amdgcn_readfirstlane(blk * 4 + wave);
   const int slot = __builtin_amdgcn_readfirstlane(sid / g.n_sc);
   const int k = __builtin_amdgcn_readfirstlane(sid - slot * g.n_sc);
   const int nq = NR >> 4;       // lane groups that carry antennas
   const bool qv = q < nq;
   const int qc = qv ? q : nq - 1;  // clamped: every address below is in bounds
 
-  // ---- 1./2. issue every load of this subcarrier before using any of them ----------------
+  // ---- 1. the block's channel rows, staged once in LDS -------------------------------------
+  // The 4 waves take subcarriers k0 .. k0+3 of one slot (n_sc is a multiple of 4).  With a
+  // pilot-resolution estimate they need pilot rows jlo .. jhi only (at most 4 for comb 2,
+  // 3 for comb 8); with a full-resolution one, rows k0 .. k0+3.  A row [rx][layer] is
+  // contiguous, so the copy is one contiguous run read with 16-byte loads.
+  const int k0 = k - wave;
+  int jlo, nrow;
+  if (HRES == 0) {
+    const int C = g.comb, L = g.comb_log2;
+    jlo = (k0 + 1 - C) < 0 ? 0 : ((k0 + 1 - C) >> L);
+    const int jhi = min(g.n_pilot - 1, ((k0 + 3) >> L) + 1);
+    nrow = jhi - jlo + 1;
+  } else {
+    jlo = k0;
+    nrow = 4;
+  }
+  {
+    const int row_f4 = (NR * NL) >> 1;
+    const int64_t row0 = (int64_t)slot * (HRES == 0 ? g.n_pilot : g.n_sc) + jlo;
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(h + row0 * NR * NL);
+    float4* __restrict__ dst = reinterpret_cast<float4*>(lds_h);
+    const int n4 = nrow * row_f4;
+    for (int f = threadIdx.x; f < n4; f += 256) dst[f] = src[f];
+  }
+  __syncthreads();
+
   // Channel, lane (q, p = c), step s: antenna 16 q + s.  Layers past NL read layer NL-1; the
   // Gram rows and columns they produce are replaced by an identity block below.
   const int pc = c < NL ? c : NL - 1;
   float2 h0[16], h1[16];
   float a = 0.f;
-  if (HRES == 0) {
-    int j0, j1;
-    freq_rule(g, pc, k, j0, j1, a);
-    const float2* __restrict__ b0 = h + ((int64_t)(slot * g.n_pilot + j0) * NR + 16 * qc) * NL + pc;
-    const float2* __restrict__ b1 = h + ((int64_t)(slot * g.n_pilot + j1) * NR + 16 * qc) * NL + pc;
+  {
+    int r0 = k - k0, r1 = r0;
+    if (HRES == 0) {
+      int j0, j1;
+      freq_rule(g, pc, k, j0, j1, a);
+      r0 = j0 - jlo;
+      r1 = j1 - jlo;
+    }
+    const float2* __restrict__ b0 = lds_h + (r0 * NR + 16 * qc) * NL + pc;
+    const float2* __restrict__ b1 = lds_h + (r1 * NR + 16 * qc) * NL + pc;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       h0[s] = b0[s * NL];
-      h1[s] = b1[s * NL];
+      if (HRES == 0) h1[s] = b1[s * NL];
     }
-  } else {
-    const float2* __restrict__ b0 = h + ((int64_t)(slot * g.n_sc + k) * NR + 16 * qc) * NL + pc;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) h0[s] = b0[s * NL];
   }
   // Received samples, lane (q, d = c): antennas 16 q .. 16 q + 15 of data symbol d (128 B).
   // Symbols past ND read symbol ND-1; their Z columns are never stored.
@@ -287,18 +314,28 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   const int d = c;
   if (live && d < ND) {
     const int64_t o = ((int64_t)(slot * ND + d) * g.n_sc + k) * NL;
+    float xo[8], vo[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int l = 4 * q + v;
-      if (l < NL) {
-        const float sd = s2 * dl[v];
-        const float im = __builtin_amdgcn_rcpf(1.f - sd);
-        if (ok) {
-          x[o + l] = make_float2(acc_xr[v] * im, acc_xi[v] * im);
-          nv[o + l] = sd * im;
-        } else {
-          x[o + l] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-          nv[o + l] = __builtin_inff();
+      const float sd = s2 * dl[v];
+      const float im = __builtin_amdgcn_rcpf(1.f - sd);
+      xo[2 * v] = ok ? acc_xr[v] * im : __builtin_nanf("");
+      xo[2 * v + 1] = ok ? acc_xi[v] * im : __builtin_nanf("");
+      vo[v] = ok ? sd * im : __builtin_inff();
+    }
+    if (NL % 4 == 0) {  // layers 4q .. 4q+3 are 32 contiguous bytes of x, 16 of nv
+      if (4 * q >= NL) return;  // lane groups of padded layers store nothing
+      float4* __restrict__ xd = reinterpret_cast<float4*>(x + o + 4 * q);
+      xd[0] = make_float4(xo[0], xo[1], xo[2], xo[3]);
+      xd[1] = make_float4(xo[4], xo[5], xo[6], xo[7]);
+      *reinterpret_cast<float4*>(nv + o + 4 * q) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int l = 4 * q + v;
+        if (l < NL) {
+          x[o + l] = make_float2(xo[2 * v], xo[2 * v + 1]);
+          nv[o + l] = vo[v];
         }
       }
     }
@@ -332,9 +369,12 @@ void launch_nl(const Geom& g, dim3 grid, const float2* rx, const float2* h, cons
 
 }  // namespace
 
-bool mmse_mfma_eligible(const Geom& g, const void* rx) {
-  // 16-byte aligned received grid: each lane reads its antennas with 16-byte loads.
-  return ((uintptr_t)rx & 15u) == 0 && g.n_occ == 1 && g.n_layers >= 5 && g.n_layers <= 16 &&
+bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
+                        const void* nv) {
+  // 16-byte aligned buffers: 16-byte loads of the received grid and channel rows, 16-byte
+  // stores of x and nv.
+  const uintptr_t mis = ((uintptr_t)rx | (uintptr_t)h | (uintptr_t)x | (uintptr_t)nv) & 15u;
+  return mis == 0 && g.n_occ == 1 && g.n_layers >= 5 && g.n_layers <= 16 &&
          g.n_rx % 16 == 0 && g.n_rx <= 64 && g.n_dsym <= 16;
 }
 

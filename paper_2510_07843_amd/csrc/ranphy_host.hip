@@ -12,7 +12,8 @@ namespace ranphy {
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
                             const float* noise_var, float2* x, float* nv, hipStream_t s);
-bool mmse_mfma_eligible(const Geom& g, const void* rx);
+bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
+                        const void* nv);
 
 namespace {
 
@@ -154,7 +155,7 @@ int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* 
   const float2* h2 = reinterpret_cast<const float2*>(h);
   float2* x2 = reinterpret_cast<float2*>(x);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ranphy::mmse_mfma_eligible(g, rx))
+  if (ranphy::mmse_mfma_eligible(g, rx, h, x, nv))
     return ranphy::status_of(ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, s));
   return ranphy::status_of(ranphy::launch_mmse_re(g, rx2, h2, h_res, noise_var, x2, nv, s));
 }
