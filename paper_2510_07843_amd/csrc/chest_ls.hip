@@ -5,7 +5,7 @@
 //   k = (p mod C) + C j,
 // and for the full-resolution output the linear interpolation between the port's two
 // nearest pilots.  Output order [..][rx][layer] puts consecutive threads on consecutive
-// layers of one antenna, so the writes are contiguous.
+// layers of one antenna, so the writes are contiguous.  Comb C <= 8, Nr <= 64, Nl <= 16.
 #include "geom.h"
 
 namespace ranphy {
@@ -30,23 +30,55 @@ __device__ __forceinline__ float2 ls_at(const Geom& g, const float2* __restrict_
   return make_float2(acc.x * inv, acc.y * inv);
 }
 
+// Pilot resolution: one block per (slot, occasion, pilot index j).  The C subcarriers
+// C j .. C j + C - 1 hold pilot j of every comb offset; their samples on the T DMRS symbols
+// (C x Nr contiguous values per symbol) are read with consecutive threads on consecutive
+// values into LDS, rows padded by one value so that threads of different comb offsets read
+// different banks, and the Nr x Nl output row h[j][rx][layer] is written contiguously.
 template <int T>
 __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* __restrict__ rx,
                                                           const float2* __restrict__ pil,
                                                           float2* __restrict__ h) {
-  const int64_t total = (int64_t)g.n_slots * g.n_occ * g.n_pilot * g.n_rx * g.n_layers;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  const int p = (int)(e % g.n_layers);
-  int64_t q = e / g.n_layers;
-  const int r = (int)(q % g.n_rx);
-  q /= g.n_rx;
-  const int j = (int)(q % g.n_pilot);
-  q /= g.n_pilot;
-  const int o = (int)(q % g.n_occ);
-  const int64_t slot = q / g.n_occ;
-  const int k = (p & (g.comb - 1)) + g.comb * j;
-  h[e] = (k < g.n_sc) ? ls_at<T>(g, rx, pil, slot, o, j, r, p) : make_float2(0.f, 0.f);
+  __shared__ float2 ys[T * 8 * (kMaxRx + 1)];
+  __shared__ float2 ps[T * kMaxLayers];
+  const int C = g.comb, NR = g.n_rx, NL = g.n_layers;
+  const int j = blockIdx.x % g.n_pilot;
+  const int so = blockIdx.x / g.n_pilot;  // slot * n_occ + occasion
+  const int o = so % g.n_occ;
+  const int64_t slot = so / g.n_occ;
+  const int n_in = T * C * NR;
+  for (int f = threadIdx.x; f < n_in; f += 256) {
+    const int t = f / (C * NR);
+    const int rem = f - t * (C * NR);
+    const int c = rem / NR;
+    const int r = rem - c * NR;
+    const int k = C * j + c;
+    float2 v = make_float2(0.f, 0.f);
+    if (k < g.n_sc) v = rx[((slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k) * NR + r];
+    ys[(t * C + c) * (NR + 1) + r] = v;
+  }
+  if (threadIdx.x < T * NL) {
+    const int t = threadIdx.x / NL, p = threadIdx.x - t * NL;
+    ps[threadIdx.x] = pil[(((int64_t)so * T + t) * g.n_pilot + j) * NL + p];
+  }
+  __syncthreads();
+  float2* __restrict__ dst = h + ((int64_t)so * g.n_pilot + j) * NR * NL;
+  const float inv = 1.f / (float)T;
+  for (int e = threadIdx.x; e < NR * NL; e += 256) {
+    const int r = e / NL;
+    const int p = e - r * NL;
+    const int c = p & (C - 1);
+    float2 acc = make_float2(0.f, 0.f);
+    if (C * j + c < g.n_sc) {
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float2 m = cmulc(ps[t * NL + p], ys[(t * C + c) * (NR + 1) + r]);  // y conj(q)
+        acc.x += m.x;
+        acc.y += m.y;
+      }
+    }
+    dst[e] = make_float2(acc.x * inv, acc.y * inv);
+  }
 }
 
 template <int T>
@@ -81,8 +113,9 @@ hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots
   if (total == 0) return hipSuccess;
   const dim3 block(256), grid((unsigned)((total + 255) / 256));
   if (h_res == 0) {
-    if (g.td == 1) hipLaunchKernelGGL(chest_pilot_kernel<1>, grid, block, 0, s, g, rx, pilots, h);
-    else hipLaunchKernelGGL(chest_pilot_kernel<2>, grid, block, 0, s, g, rx, pilots, h);
+    const dim3 pgrid((unsigned)((int64_t)g.n_slots * g.n_occ * g.n_pilot));
+    if (g.td == 1) hipLaunchKernelGGL(chest_pilot_kernel<1>, pgrid, block, 0, s, g, rx, pilots, h);
+    else hipLaunchKernelGGL(chest_pilot_kernel<2>, pgrid, block, 0, s, g, rx, pilots, h);
   } else {
     if (g.td == 1) hipLaunchKernelGGL(chest_full_kernel<1>, grid, block, 0, s, g, rx, pilots, h);
     else hipLaunchKernelGGL(chest_full_kernel<2>, grid, block, 0, s, g, rx, pilots, h);
