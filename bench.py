@@ -29,6 +29,27 @@ FP32_VALU_PEAK_TFLOPS = 78.6     # FP32 vector FMA without packed-FP32 instructi
 
 CMAC = 8  # real flops per complex multiply-accumulate
 
+PROFILES = os.path.join(ROOT, "profiles")
+DETECTOR_SOURCES = ("paper_2510_07843_amd/csrc/mmse_mfma.hip", "paper_2510_07843_amd/csrc/geom.h")
+
+
+def measured_traffic(tag: str):
+    """HBM bytes per mmse_detect launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary for this workload, or None when there is none or the detector's source has
+    changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(PROFILES, f"traffic_mmse_detect_{tag}.md")
+    if not os.path.exists(path):
+        return None
+    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines()
+                  if l.startswith("mmse_detect_"))
+    h = hashlib.sha256()
+    for f in DETECTOR_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("mmse_detect_source_sha256") != h.hexdigest():
+        return None
+    return float(fields["mmse_detect_traffic_bytes_per_launch"])
+
 
 def algorithmic_costs(shape, h_res=0):
     """Per-launch algorithmic HBM bytes and flops of each call (each input read once, each
@@ -178,7 +199,11 @@ def main():
                     achieved=c["flops"] / sec / 1e12, peak=compute_peak, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
-    roof["traffic"] = None
+    tag = f"{shape.n_rx}x{shape.n_layers}_{shape.n_slots}slots"
+    roof["traffic"] = (measured_traffic(tag) if (dom == "mmse_detect" and h_res == ranphy.H_PILOT)
+                       else None)
+    roof["algorithmic_bytes"] = c["bytes"]
+    roof["algorithmic_flops"] = c["flops"]
 
     out = {
         "metric": "REs/s detected, 64Rx×16L MMSE: FP32 plain vs mixed/learned at ≤0.1 dB loss",
