@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--workload", default="m", choices=["m", "c2", "c1"])
     ap.add_argument("--slots", type=int, default=None, help="override the batch size")
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="input precision of the detector's Gram and matched filter")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
@@ -135,6 +137,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
     shape = b["shape"]
     h_res = ranphy.H_PILOT if args.h_res == "pilot" else ranphy.H_FULL
+    prec = {"fp32": ranphy.PREC_FP32, "fp16": ranphy.PREC_FP16, "bf16": ranphy.PREC_BF16}[args.prec]
     print(f"# workload {args.workload}: {shape.n_slots} slots {shape.n_rx}x{shape.n_layers} "
           f"{shape.n_prb} PRB qm={shape.qm}; generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -158,7 +161,7 @@ def main():
         ranphy.chest_ls(shape, rx, pil, h=h, h_res=h_res)
         if record:
             marks[1].record()
-        ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv)
+        ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv, precision=prec)
         if record:
             marks[2].record()
         ranphy.llr_demap(shape, x, nv, llr=llr)

@@ -81,6 +81,14 @@ enum {
   RANPHY_ERR_LAUNCH = -3       /* the HIP runtime refused a launch (no device, ...)     */
 };
 
+/* Input precision of the Gram and matched-filter products in ranphy_mmse_detect_prec.
+ * Accumulation, inversion, solve and unbiasing are FP32 in every mode. */
+enum {
+  RANPHY_PREC_FP32 = 0, /* FP32 inputs (the plain path; what ranphy_mmse_detect does)      */
+  RANPHY_PREC_FP16 = 1, /* inputs rounded to FP16, FP32 accumulation on the matrix cores  */
+  RANPHY_PREC_BF16 = 2  /* inputs rounded to BF16, FP32 accumulation on the matrix cores  */
+};
+
 /* Buffer identifiers for ranphy_buffer_floats. */
 enum {
   RANPHY_BUF_RX = 0,        /* [slot][symb][sc][rx]           complex64 */
@@ -134,6 +142,20 @@ RANPHY_API int ranphy_chest_ls(const ranphy_slot_desc* d, const float* rx, const
  */
 RANPHY_API int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
                        const float* noise_var, float* x, float* nv, void* stream);
+
+/*
+ * ranphy_mmse_detect with a choice of input precision for the two contractions over the
+ * receive antennas (the Gram H^H H and the matched filter H^H y): the paper's point that
+ * reduced precision keeps detection accuracy (Sec. III-A: 16-bit real/imaginary parts are
+ * often enough; Sec. IV, Fig. 5(a): single precision matches double), taken to 16-bit
+ * matrix-core inputs.  Same arguments, layouts and outputs as ranphy_mmse_detect.
+ * RANPHY_PREC_FP16 / RANPHY_PREC_BF16 run only on the matrix-core detector: one DMRS
+ * occasion, 5..16 layers, n_rx a multiple of 16, rx / h / x / nv 16-byte aligned; other
+ * shapes return RANPHY_ERR_UNSUPPORTED.  RANPHY_PREC_FP32 accepts every shape.
+ */
+RANPHY_API int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx,
+                                       const float* h, int h_res, const float* noise_var,
+                                       float* x, float* nv, int precision, void* stream);
 
 /*
  * Max-log LLRs of Gray square QAM (3GPP NR mapping structure: bits b0, b2, .. on the

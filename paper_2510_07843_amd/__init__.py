@@ -26,12 +26,13 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libranphy.so")
 
 H_PILOT, H_FULL = 0, 1
+PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_LAUNCH = 0, -1, -2, -3
 BUF_RX, BUF_PILOTS, BUF_H, BUF_NOISE_VAR, BUF_X, BUF_NV, BUF_LLR = range(7)
 
 EXPORTED_SYMBOLS = (
     "ranphy_abi_version", "ranphy_status_str", "ranphy_buffer_floats",
-    "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_llr_demap",
+    "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_llr_demap",
 )
 
 
@@ -85,8 +86,10 @@ def lib() -> ctypes.CDLL:
         L.ranphy_buffer_floats.restype = ctypes.c_int64
         L.ranphy_chest_ls.argtypes = [D, P, P, P, ctypes.c_int, P]
         L.ranphy_mmse_detect.argtypes = [D, P, P, ctypes.c_int, P, P, P, P]
+        L.ranphy_mmse_detect_prec.argtypes = [D, P, P, ctypes.c_int, P, P, P, ctypes.c_int, P]
         L.ranphy_llr_demap.argtypes = [D, P, P, P, P]
-        for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_llr_demap"):
+        for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
+                  "ranphy_llr_demap"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -155,8 +158,12 @@ def chest_ls(shape, rx: torch.Tensor, pilots: torch.Tensor, h: Optional[torch.Te
 
 def mmse_detect(shape, rx: torch.Tensor, h: torch.Tensor, noise_var: torch.Tensor,
                 h_res: int = H_PILOT, x: Optional[torch.Tensor] = None,
-                nv: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Unbiased LMMSE symbols and post-equalisation variances, [slot][dsym][sc][layer]."""
+                nv: Optional[torch.Tensor] = None, stream=None,
+                precision: int = PREC_FP32) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Unbiased LMMSE symbols and post-equalisation variances, [slot][dsym][sc][layer].
+
+    ``precision`` selects the input precision of the Gram and matched-filter products
+    (PREC_FP32, PREC_FP16, PREC_BF16); the 16-bit modes need the matrix-core shapes."""
     d = desc_of(shape)
     nx = buffer_floats(d, BUF_X)
     if x is None:
@@ -168,8 +175,12 @@ def mmse_detect(shape, rx: torch.Tensor, h: torch.Tensor, noise_var: torch.Tenso
     pn = _as_dev(noise_var, "noise_var", torch.float32, buffer_floats(d, BUF_NOISE_VAR))
     px = _as_dev(x, "x", torch.complex64, nx)
     pv = _as_dev(nv, "nv", torch.float32, buffer_floats(d, BUF_NV))
-    _check("ranphy_mmse_detect", lib().ranphy_mmse_detect(ctypes.byref(d), *args, h_res, pn, px, pv,
-                                                          _stream(stream)))
+    if precision == PREC_FP32:
+        st = lib().ranphy_mmse_detect(ctypes.byref(d), *args, h_res, pn, px, pv, _stream(stream))
+    else:
+        st = lib().ranphy_mmse_detect_prec(ctypes.byref(d), *args, h_res, pn, px, pv, precision,
+                                           _stream(stream))
+    _check("ranphy_mmse_detect", st)
     return x, nv
 
 

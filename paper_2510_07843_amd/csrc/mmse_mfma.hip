@@ -36,12 +36,57 @@ namespace ranphy {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Precision of the Gram and matched-filter products (inputs; accumulation is always FP32).
+enum { kPrecF32 = 0, kPrecF16 = 1, kPrecBF16 = 2 };
 
 constexpr float kPivotRel = 16.f * FLT_EPSILON;
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma(half8 a, half8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight FP32 values rounded to the MFMA input type (round to nearest even).
+template <typename V, typename E>
+__device__ __forceinline__ V pack8(const float* v, float sign) {
+  V r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (E)(sign * v[e]);
+  return r;
+}
+
+// Gram and matched filter in a 16-bit input type on v_mfma_f32_16x16x32_{f16,bf16}: step t
+// covers antennas 16 q + 8 t .. 16 q + 8 t + 7 of lane group q (both operands in the same
+// element order, so the K ordering inside an instruction does not matter).
+template <typename V, typename E>
+__device__ __forceinline__ void gram_mf_lowp(const float (&hr)[16], const float (&hi)[16],
+                                             const float (&yr)[16], const float (&yi)[16],
+                                             floatx4& acc_g, floatx4& acc_p, floatx4& zr,
+                                             floatx4& zi) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const V a_r = pack8<V, E>(hr + 8 * t, 1.f);
+    const V a_i = pack8<V, E>(hi + 8 * t, 1.f);
+    const V a_n = pack8<V, E>(hi + 8 * t, -1.f);
+    const V b_r = pack8<V, E>(yr + 8 * t, 1.f);
+    const V b_i = pack8<V, E>(yi + 8 * t, 1.f);
+    acc_g = mfma(a_r, a_r, acc_g);
+    acc_g = mfma(a_i, a_i, acc_g);
+    acc_p = mfma(a_r, a_i, acc_p);
+    zr = mfma(a_r, b_r, zr);
+    zr = mfma(a_i, b_i, zr);
+    zi = mfma(a_r, b_i, zi);
+    zi = mfma(a_n, b_r, zi);
+  }
 }
 
 // Value of lane SRC of each row of 16 lanes (DPP row_newbcast; a VALU move, no LDS trip).
@@ -130,7 +175,7 @@ __device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16])
   }
 }
 
-template <int HRES, int NL>
+template <int HRES, int NL, int PREC>
 __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
                                                         const float* __restrict__ nvar,
@@ -245,18 +290,30 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   }
 
   // ---- 3. Gram and matched filter on the matrix cores -------------------------------------
-  // Z = H^H Y with three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
+  // FP32: Z = H^H Y with three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
   //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
-  floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, acc_m1 = acc_g, acc_m2 = acc_g,
-          acc_m3 = acc_g;
+  // 16-bit inputs: four products, no cancellation on top of the input rounding.
+  floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, z_r = acc_g, z_i = acc_g;
+  if constexpr (PREC == kPrecF32) {
+    floatx4 acc_m1 = acc_g, acc_m2 = acc_g, acc_m3 = acc_g;
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    acc_g = mfma(hr[s], hr[s], acc_g);
-    acc_g = mfma(hi[s], hi[s], acc_g);
-    acc_p = mfma(hr[s], hi[s], acc_p);
-    acc_m1 = mfma(hr[s], yr[s], acc_m1);
-    acc_m2 = mfma(hi[s], yi[s], acc_m2);
-    acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
+    for (int s = 0; s < 16; ++s) {
+      acc_g = mfma(hr[s], hr[s], acc_g);
+      acc_g = mfma(hi[s], hi[s], acc_g);
+      acc_p = mfma(hr[s], hi[s], acc_p);
+      acc_m1 = mfma(hr[s], yr[s], acc_m1);
+      acc_m2 = mfma(hi[s], yi[s], acc_m2);
+      acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      z_r[v] = acc_m1[v] + acc_m2[v];
+      z_i[v] = acc_m3[v] - acc_m1[v] + acc_m2[v];
+    }
+  } else if constexpr (PREC == kPrecF16) {
+    gram_mf_lowp<half8, _Float16>(hr, hi, yr, yi, acc_g, acc_p, z_r, z_i);
+  } else {
+    gram_mf_lowp<bf16x8, __bf16>(hr, hi, yr, yi, acc_g, acc_p, z_r, z_i);
   }
 
   // ---- 4. G = Re + j (P - P^T) + s2 I, padded layers -> identity; invert in place ---------
@@ -294,8 +351,8 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   floatx4 acc_n1 = {0.f, 0.f, 0.f, 0.f}, acc_n2 = acc_n1, acc_n3 = acc_n1;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const float zr = acc_m1[s] + acc_m2[s];
-    const float zi = acc_m3[s] - acc_m1[s] + acc_m2[s];
+    const float zr = z_r[s];
+    const float zi = z_i[s];
     acc_n1 = mfma(ar[s], zr, acc_n1);
     acc_n2 = mfma(ai[s], zi, acc_n2);
     acc_n3 = mfma(ar[s] - ai[s], zr + zi, acc_n3);
@@ -342,29 +399,37 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   }
 }
 
-template <int HRES, int NL>
+template <int HRES, int NL, int PREC>
 void launch_one(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
                 float2* x, float* nv, hipStream_t s) {
-  hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL>), grid, dim3(256), 0, s, g, rx, h, nvar, x, nv);
+  hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC>), grid, dim3(256), 0, s, g, rx, h, nvar,
+                     x, nv);
 }
 
-template <int HRES>
+template <int HRES, int PREC>
 void launch_nl(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
                float2* x, float* nv, hipStream_t s) {
   switch (g.n_layers) {
-    case 5: launch_one<HRES, 5>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 6: launch_one<HRES, 6>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 7: launch_one<HRES, 7>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 8: launch_one<HRES, 8>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 9: launch_one<HRES, 9>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 10: launch_one<HRES, 10>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 11: launch_one<HRES, 11>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 12: launch_one<HRES, 12>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 13: launch_one<HRES, 13>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 14: launch_one<HRES, 14>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 15: launch_one<HRES, 15>(g, grid, rx, h, nvar, x, nv, s); break;
-    default: launch_one<HRES, 16>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    default: launch_one<HRES, 16, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
   }
+}
+
+template <int PREC>
+void launch_prec(const Geom& g, dim3 grid, const float2* rx, const float2* h, int h_res,
+                 const float* nvar, float2* x, float* nv, hipStream_t s) {
+  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, h, nvar, x, nv, s);
+  else launch_nl<1, PREC>(g, grid, rx, h, nvar, x, nv, s);
 }
 
 }  // namespace
@@ -379,12 +444,16 @@ bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void
 }
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
-                            const float* nvar, float2* x, float* nv, hipStream_t s) {
+                            const float* nvar, float2* x, float* nv, int prec, hipStream_t s) {
   const int64_t waves = (int64_t)g.n_slots * g.n_sc;
   const int64_t blocks = (waves + 3) / 4;
   const dim3 grid((unsigned)((blocks + kXcds - 1) / kXcds * kXcds));
-  if (h_res == 0) launch_nl<0>(g, grid, rx, h, nvar, x, nv, s);
-  else launch_nl<1>(g, grid, rx, h, nvar, x, nv, s);
+  switch (prec) {
+    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, h, h_res, nvar, x, nv, s); break;
+    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, h, h_res, nvar, x, nv, s); break;
+    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, h, h_res, nvar, x, nv, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@
 namespace ranphy {
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
-                            const float* noise_var, float2* x, float* nv, hipStream_t s);
+                            const float* noise_var, float2* x, float* nv, int prec,
+                            hipStream_t s);
 bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
                         const void* nv);
 
@@ -141,12 +142,16 @@ int ranphy_chest_ls(const ranphy_slot_desc* d, const float* rx, const float* pil
       reinterpret_cast<float2*>(h), h_res, static_cast<hipStream_t>(stream)));
 }
 
-int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
-                       const float* noise_var, float* x, float* nv, void* stream) {
+int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx, const float* h,
+                            int h_res, const float* noise_var, float* x, float* nv,
+                            int precision, void* stream) {
   Geom g;
   const int rc = ranphy::make_geom(d, &g);
   if (rc) return rc;
   if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+  if (precision != RANPHY_PREC_FP32 && precision != RANPHY_PREC_FP16 &&
+      precision != RANPHY_PREC_BF16)
+    return RANPHY_ERR_INVALID;
   if (g.n_slots == 0) return RANPHY_OK;
   if (!ranphy::aligned8(rx) || !ranphy::aligned8(h) || !ranphy::aligned8(x) ||
       !ranphy::aligned8(nv) || noise_var == nullptr || ((uintptr_t)noise_var & 3u))
@@ -155,9 +160,17 @@ int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* 
   const float2* h2 = reinterpret_cast<const float2*>(h);
   float2* x2 = reinterpret_cast<float2*>(x);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (ranphy::mmse_mfma_eligible(g, rx, h, x, nv))
-    return ranphy::status_of(ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, s));
+  const bool mfma = ranphy::mmse_mfma_eligible(g, rx, h, x, nv);
+  if (precision != RANPHY_PREC_FP32 && !mfma) return RANPHY_ERR_UNSUPPORTED;
+  if (mfma)
+    return ranphy::status_of(
+        ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, precision, s));
   return ranphy::status_of(ranphy::launch_mmse_re(g, rx2, h2, h_res, noise_var, x2, nv, s));
+}
+
+int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
+                       const float* noise_var, float* x, float* nv, void* stream) {
+  return ranphy_mmse_detect_prec(d, rx, h, h_res, noise_var, x, nv, RANPHY_PREC_FP32, stream);
 }
 
 int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const float* nv, float* llr,

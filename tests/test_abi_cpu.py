@@ -134,3 +134,19 @@ def test_binding_refuses_host_tensors(L):
     pil = torch.zeros(ranphy.buffer_floats(sh, ranphy.BUF_PILOTS) // 2, dtype=torch.complex64)
     with pytest.raises(ValueError, match="GPU tensor"):
         ranphy.chest_ls(sh, rx, pil, h=torch.zeros(1, dtype=torch.complex64))
+
+
+def test_reduced_precision_rejected_off_the_matrix_core_shapes(L):
+    P = ctypes.c_void_p
+    # Two DMRS occasions (time-varying channel): only the FP32 path takes it.
+    d = _desc(n_rx=16, n_layers=8, dmrs_comb=4, dmrs_td=2, dmrs_sym0=(2, 10))
+    for prec in (1, 2):
+        assert L.ranphy_mmse_detect_prec(ctypes.byref(d), P(0x1000), P(0x1000), 0, P(0x1000),
+                                         P(0x1000), P(0x1000), prec, None) == -2
+    # Four layers: below the matrix-core range.
+    d = _desc(n_rx=16, n_layers=4)
+    assert L.ranphy_mmse_detect_prec(ctypes.byref(d), P(0x1000), P(0x1000), 0, P(0x1000),
+                                     P(0x1000), P(0x1000), 1, None) == -2
+    # Unknown precision code.
+    assert L.ranphy_mmse_detect_prec(ctypes.byref(d), P(0x1000), P(0x1000), 0, P(0x1000),
+                                     P(0x1000), P(0x1000), 7, None) == -1

@@ -324,3 +324,32 @@ def test_fp32_ber_matches_fp64_over_c2_sweep():
         n = int(b["bits"][sel].size)
         say(f"SNR {synth.CONFIGS['c2']['snr_db'][i]} dB: BER fp32 {eg / n:.3e} fp64 {er / n:.3e}")
         assert abs(eg - er) <= 3 * math.sqrt(er + 1) + 5
+
+
+def sinr_db(xhat, x):
+    return 10 * np.log10(np.mean(np.abs(x) ** 2) / np.mean(np.abs(xhat - x) ** 2))
+
+
+def test_reduced_precision_sinr_loss_64x16():
+    # 64 Rx x 16 layers, one slot at each SNR of 0..30 dB.  The Gram and matched filter with
+    # FP16 or BF16 inputs (FP32 accumulation) must stay within 0.1 dB of the FP64 oracle's
+    # post-equalisation SINR; the EVM of each path against the oracle is printed.
+    b = synth.make_batch("m", n_slots=7, workers=8)
+    shape = b["shape"]
+    h = oracle.chest_ls(shape, b["rx"], b["pilots"]).astype(np.complex64)
+    xr, _ = oracle.mmse_detect(shape, b["rx"], h, ranphy.H_PILOT, b["noise_var"])
+    out = {}
+    for name, prec in (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16),
+                       ("bf16", ranphy.PREC_BF16)):
+        x, _ = ranphy.mmse_detect(shape, dev(b["rx"]), dev(h), dev(b["noise_var"]), precision=prec)
+        out[name] = host(x, out_shape(shape))
+    for i, snr in enumerate(b["snr_db"]):
+        ref = sinr_db(xr[i], b["x"][i])
+        line = [f"SNR {snr:4.1f} dB: SINR fp64 {ref:6.2f}"]
+        for name in ("fp32", "fp16", "bf16"):
+            s = sinr_db(out[name][i], b["x"][i])
+            evm = 10 * np.log10(np.mean(np.abs(out[name][i] - xr[i]) ** 2) / np.mean(np.abs(xr[i]) ** 2))
+            line.append(f"{name} {s:6.2f} (loss {ref - s:+.3f} dB, EVM vs fp64 {evm:6.1f} dB)")
+            limit = 0.005 if name == "fp32" else 0.1
+            assert ref - s <= limit, (name, snr, ref, s)
+        say("; ".join(line))
