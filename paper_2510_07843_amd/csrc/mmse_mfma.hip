@@ -138,8 +138,8 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& s
   // Row K at this lane's column c (row group K/4, register K%4), scaled; zero in the pivot
   // column so that the rank-1 update leaves that column untouched.
   const bool col_k = (c == K);
-  const float rw = group_bcast<KQ>(ar[KV]);
-  const float iw = group_bcast<KQ>(ai[KV]);
+  const float rw = lane_read(ar[KV], 16 * KQ + c);  // ds_bpermute: no VALU work
+  const float iw = lane_read(ai[KV], 16 * KQ + c);
   const float rr = col_k ? 0.f : rw * pinv;
   const float ri = col_k ? 0.f : iw * pinv;
   scale = col_k ? -pinv : scale;
@@ -277,9 +277,11 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
       hi[s] = h0[s].y;
     }
   }
-  if (!qv) {  // antenna groups past NR contribute nothing
+  if (nq < 4) {  // wave-uniform: only fewer than 64 antennas need masking
+    if (!qv) {  // antenna groups past NR contribute nothing
 #pragma unroll
-    for (int s = 0; s < 16; ++s) hr[s] = hi[s] = 0.f;
+      for (int s = 0; s < 16; ++s) hr[s] = hi[s] = 0.f;
+    }
   }
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
