@@ -353,3 +353,24 @@ def test_reduced_precision_sinr_loss_64x16():
             limit = 0.005 if name == "fp32" else 0.1
             assert ref - s <= limit, (name, snr, ref, s)
         say("; ".join(line))
+
+
+def test_llr_demap_8_byte_aligned_buffers():
+    # Buffers 8- but not 16-byte aligned take the one-element-per-thread kernel.
+    qm = 6
+    shape = SlotShape(3, 14, 4, 3, qm, 4, 1, (2,), 1)
+    rng = np.random.default_rng(11)
+    n = out_shape(shape)
+    x = ((rng.standard_normal(n) + 1j * rng.standard_normal(n)) * 0.8).astype(np.complex64)
+    nv = rng.uniform(1e-3, 2.0, n).astype(np.float32)
+    xb = torch.zeros(x.size + 1, dtype=torch.complex64, device="cuda")
+    vb = torch.zeros(nv.size + 2, dtype=torch.float32, device="cuda")
+    lb = torch.zeros(nv.size * qm + 2, dtype=torch.float32, device="cuda")
+    xb[1:] = dev(x)
+    vb[2:] = dev(nv)
+    xv, vv, lv = xb[1:], vb[2:], lb[2:]
+    assert xv.data_ptr() % 16 == 8 and vv.data_ptr() % 16 == 8 and lv.data_ptr() % 16 == 8
+    ranphy.llr_demap(shape, xv, vv, llr=lv)
+    lg = host(lv, n + (qm,))
+    lr = oracle.llr_demap(shape, x, nv)
+    assert llr_tol_ok(lg, lr).all()
