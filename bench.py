@@ -97,6 +97,41 @@ def cpu_baseline(b, budget_s: float):
                        f"chest_ls + mmse_detect (LU route) + llr_demap in FP64, {dt:.1f} s")
 
 
+def detection_quality(torch, ranphy, synth):
+    """Post-equalisation SINR of each detector precision and of the FP64 oracle on one slot
+    per SNR point of the 64 x 16 workload (the same seeded slots as the batch's first 7)."""
+    import oracle
+    t = synth.make_batch("m", n_slots=len(synth.CONFIGS["m"]["snr_db"]), workers=8)
+    sh = t["shape"]
+    hq = oracle.chest_ls(sh, t["rx"], t["pilots"]).astype(np.complex64)
+    xr, _ = oracle.mmse_detect(sh, t["rx"], hq, oracle.H_PILOT, t["noise_var"])
+    dev = torch.device("cuda:0")
+    rx = torch.from_numpy(t["rx"]).to(dev).reshape(-1)
+    pil = torch.from_numpy(t["pilots"]).to(dev).reshape(-1)
+    nvar = torch.from_numpy(t["noise_var"]).to(dev)
+
+    def sinr(xh, x):
+        return 10 * np.log10(np.mean(np.abs(x) ** 2) / np.mean(np.abs(xh - x) ** 2))
+
+    ref = [sinr(xr[i], t["x"][i]) for i in range(sh.n_slots)]
+    out = {}
+    for name, p in (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16),
+                    ("bf16", ranphy.PREC_BF16)):
+        hg = ranphy.chest_ls(sh, rx, pil)
+        xg, _ = ranphy.mmse_detect(sh, rx, hg, nvar, precision=p)
+        torch.cuda.synchronize()
+        xg = xg.cpu().numpy().reshape(xr.shape)
+        s = [sinr(xg[i], t["x"][i]) for i in range(sh.n_slots)]
+        evm = [10 * np.log10(np.mean(np.abs(xg[i] - xr[i]) ** 2) / np.mean(np.abs(xr[i]) ** 2))
+               for i in range(sh.n_slots)]
+        out[name] = {"sinr_db": [round(v, 3) for v in s],
+                     "sinr_loss_db_max": round(float(max(r - v for r, v in zip(ref, s))), 4),
+                     "evm_vs_fp64_db_max": round(float(max(evm)), 1)}
+    out["fp32"]["sinr_fp64_db"] = [round(v, 3) for v in ref]
+    out["fp32"]["snr_db"] = [float(v) for v in t["snr_db"]]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +144,8 @@ def main():
                     help="input precision of the detector's Gram and matched filter")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP16/BF16 detector runs and the SINR comparison")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -152,37 +189,41 @@ def main():
     torch.cuda.synchronize()
 
     names = ("chest_ls", "mmse_detect", "llr_demap")
-    ev = {n: [] for n in names}
 
-    def step(record):
-        marks = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
-        if record:
-            marks[0].record()
-        ranphy.chest_ls(shape, rx, pil, h=h, h_res=h_res)
-        if record:
-            marks[1].record()
-        ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv, precision=prec)
-        if record:
-            marks[2].record()
-        ranphy.llr_demap(shape, x, nv, llr=llr)
-        if record:
-            marks[3].record()
-            for i, n in enumerate(names):
-                ev[n].append((marks[i], marks[i + 1]))
+    def run_timed(precision):
+        """Warm up, then time exactly args.steps steps; returns (ms per step, per-kernel ms)."""
+        ev = {n: [] for n in names}
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record()
-    for _ in range(args.steps):
-        step(True)
-    t_end.record()
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_step = total_ms / args.steps
-    kern_ms = {n: float(np.mean([a.elapsed_time(c) for a, c in ev[n]])) for n in names}
+        def step(record):
+            marks = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+            if record:
+                marks[0].record()
+            ranphy.chest_ls(shape, rx, pil, h=h, h_res=h_res)
+            if record:
+                marks[1].record()
+            ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv, precision=precision)
+            if record:
+                marks[2].record()
+            ranphy.llr_demap(shape, x, nv, llr=llr)
+            if record:
+                marks[3].record()
+                for i, n in enumerate(names):
+                    ev[n].append((marks[i], marks[i + 1]))
+
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        t_start.record()
+        for _ in range(args.steps):
+            step(True)
+        t_end.record()
+        torch.cuda.synchronize()
+        return (t_start.elapsed_time(t_end) / args.steps,
+                {n: float(np.mean([a.elapsed_time(c) for a, c in ev[n]])) for n in names})
+
+    ms_step, kern_ms = run_timed(prec)
 
     costs = algorithmic_costs(shape, h_res)
     re = costs["data_re"]
@@ -212,11 +253,13 @@ def main():
         "metric": "REs/s detected, 64Rx×16L MMSE: FP32 plain vs mixed/learned at ≤0.1 dB loss",
         "value": value, "unit": "RE/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic (seeded TDL exponential-PDP channel, Gray QAM, AWGN)",
+        "dtype": {"fp32": "f32", "fp16": "f16 products, f32 accumulate",
+                  "bf16": "bf16 products, f32 accumulate"}[args.prec], "data": "synthetic (seeded TDL exponential-PDP channel, Gray QAM, AWGN)",
         "config": {"workload": f"{shape.n_rx}Rx x {shape.n_layers}L, {shape.n_prb} PRB x {shape.n_symb} "
                                f"symbols, qm={shape.qm}, DMRS comb {shape.dmrs_comb} x TD {shape.dmrs_td}, "
-                               f"{shape.n_slots} slots, h_res={args.h_res}, plain FP32",
-                   "slots": shape.n_slots, "data_re_per_step": re, "path": "plain_fp32"},
+                               f"{shape.n_slots} slots, h_res={args.h_res}, detector {args.prec}",
+                   "slots": shape.n_slots, "data_re_per_step": re,
+                   "path": "plain_fp32" if args.prec == "fp32" else f"mixed_{args.prec}"},
         "kernels_ms": kern_ms,
         "roofline": roof,
     }
@@ -226,6 +269,24 @@ def main():
             "GB/s": cc["bytes"] / (kern_ms[n] * 1e-3) / 1e9,
             "TFLOP/s": cc["flops"] / (kern_ms[n] * 1e-3) / 1e12,
             "bytes_per_launch": cc["bytes"], "flops_per_launch": cc["flops"]}
+    if args.workload == "m" and h_res == ranphy.H_PILOT and not args.no_variants:
+        variants = {}
+        for name, p in (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16),
+                        ("bf16", ranphy.PREC_BF16)):
+            if name == args.prec:
+                v_ms, v_k = ms_step, kern_ms
+            else:
+                v_ms, v_k = run_timed(p)
+            variants[name] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
+                              "mmse_detect_ms": v_k["mmse_detect"]}
+        quality = detection_quality(torch, ranphy, synth)
+        for name in variants:
+            variants[name].update(quality[name])
+        out["variants"] = variants
+        out["variants_note"] = ("Gram and matched filter with FP32 / FP16 / BF16 inputs (FP32 "
+                                "accumulation, FP32 inversion); SINR = E|x|^2 / E|x~ - x|^2 "
+                                "against the transmitted symbols on one slot per SNR point "
+                                "(0..30 dB), loss relative to the FP64 oracle on the same slots")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_budget)
     print(json.dumps(out), flush=True)
