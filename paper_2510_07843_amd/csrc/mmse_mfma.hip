@@ -64,36 +64,57 @@ __device__ __forceinline__ V pack8(const float* v, float sign) {
   return r;
 }
 
-// Gram and matched filter in a 16-bit input type on v_mfma_f32_16x16x32_{f16,bf16}: step t
-// covers antennas 16 q + 8 t .. 16 q + 8 t + 7 of lane group q (both operands in the same
-// element order, so the K ordering inside an instruction does not matter).
+// Channel operands in a 16-bit input type for v_mfma_f32_16x16x32_{f16,bf16}: step t covers
+// antennas 16 q + 8 t .. 16 q + 8 t + 7 of lane group q (both operands of every product use
+// the same element order, so the K ordering inside an instruction does not matter).
+template <typename V>
+struct LowpH {
+  V r[2], i[2], n[2];  // H real, imaginary, negated imaginary
+};
+
 template <typename V, typename E>
-__device__ __forceinline__ void gram_mf_lowp(const float (&hr)[16], const float (&hi)[16],
-                                             const float (&yr)[16], const float (&yi)[16],
-                                             floatx4& acc_g, floatx4& acc_p, floatx4& zr,
-                                             floatx4& zi) {
+__device__ __forceinline__ LowpH<V> pack_h(const float (&hr)[16], const float (&hi)[16]) {
+  LowpH<V> o;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const V a_r = pack8<V, E>(hr + 8 * t, 1.f);
-    const V a_i = pack8<V, E>(hi + 8 * t, 1.f);
-    const V a_n = pack8<V, E>(hi + 8 * t, -1.f);
+    o.r[t] = pack8<V, E>(hr + 8 * t, 1.f);
+    o.i[t] = pack8<V, E>(hi + 8 * t, 1.f);
+    o.n[t] = pack8<V, E>(hi + 8 * t, -1.f);
+  }
+  return o;
+}
+
+template <typename V>
+__device__ __forceinline__ void gram_lowp(const LowpH<V>& a, floatx4& acc_g, floatx4& acc_p) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    acc_g = mfma(a.r[t], a.r[t], acc_g);
+    acc_g = mfma(a.i[t], a.i[t], acc_g);
+    acc_p = mfma(a.r[t], a.i[t], acc_p);
+  }
+}
+
+// Z = H^H Y with four products (no cancellation on top of the input rounding).
+template <typename V, typename E>
+__device__ __forceinline__ void mf_lowp(const LowpH<V>& a, const float (&yr)[16],
+                                        const float (&yi)[16], floatx4& zr, floatx4& zi) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
     const V b_r = pack8<V, E>(yr + 8 * t, 1.f);
     const V b_i = pack8<V, E>(yi + 8 * t, 1.f);
-    acc_g = mfma(a_r, a_r, acc_g);
-    acc_g = mfma(a_i, a_i, acc_g);
-    acc_p = mfma(a_r, a_i, acc_p);
-    zr = mfma(a_r, b_r, zr);
-    zr = mfma(a_i, b_i, zr);
-    zi = mfma(a_r, b_i, zi);
-    zi = mfma(a_n, b_r, zi);
+    zr = mfma(a.r[t], b_r, zr);
+    zr = mfma(a.i[t], b_i, zr);
+    zi = mfma(a.r[t], b_i, zi);
+    zi = mfma(a.n[t], b_r, zi);
   }
 }
 
 // Value of lane SRC of each row of 16 lanes (DPP row_newbcast; a VALU move, no LDS trip).
 template <int SRC>
 __device__ __forceinline__ float row_bcast(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + SRC, 0xF, 0xF, false));
+  // Every lane reads a valid source lane, so bound_ctrl changes nothing; it lets the move be
+  // emitted without first materialising an "old" value.
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + SRC, 0xF, 0xF, true));
 }
 
 // Value held by row group G (lanes 16 G .. 16 G + 15) at the same position in the row, for
@@ -230,12 +251,29 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
   }
   __syncthreads();
 
+  // ---- 2. received samples: issued now, consumed only after the inversion ---------------
+  // Lane (q, d = c): antennas 16 q .. 16 q + 15 of data symbol d (128 B).  Symbols past ND
+  // read symbol ND-1; their Z columns are never stored.  The Gram and the inversion need
+  // only the channel, so this load's latency is hidden behind them.  (Issued after the
+  // block's channel copy, which every wave of the block waits for.)
+  float4 yv[8];
+  {
+    const int d = c < ND ? c : ND - 1;
+    const int s = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
+    const float4* __restrict__ src = reinterpret_cast<const float4*>(
+        rx + ((int64_t)(slot * g.n_symb + s) * g.n_sc + k) * NR + 16 * qc);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) yv[i] = src[i];
+  }
+  const float s2 = nvar[slot];
+
+
   // Channel, lane (q, p = c), step s: antenna 16 q + s.  Layers past NL read layer NL-1; the
   // Gram rows and columns they produce are replaced by an identity block below.
-  const int pc = c < NL ? c : NL - 1;
-  float2 h0[16], h1[16];
-  float a = 0.f;
+  float hr[16], hi[16];
   {
+    const int pc = c < NL ? c : NL - 1;
+    float a = 0.f;
     int r0 = k - k0, r1 = r0;
     if (HRES == 0) {
       int j0, j1;
@@ -247,34 +285,15 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
     const float2* __restrict__ b1 = lds_h + (r1 * NR + 16 * qc) * NL + pc;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      h0[s] = b0[s * NL];
-      if (HRES == 0) h1[s] = b1[s * NL];
-    }
-  }
-  // Received samples, lane (q, d = c): antennas 16 q .. 16 q + 15 of data symbol d (128 B).
-  // Symbols past ND read symbol ND-1; their Z columns are never stored.
-  float4 yv[8];
-  {
-    const int d = c < ND ? c : ND - 1;
-    const int s = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
-    const float4* __restrict__ src = reinterpret_cast<const float4*>(
-        rx + ((int64_t)(slot * g.n_symb + s) * g.n_sc + k) * NR + 16 * qc);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) yv[i] = src[i];
-  }
-  const float s2 = nvar[slot];
-  // Keep all loads of this subcarrier in flight together: one memory latency per wave.
-  __builtin_amdgcn_sched_barrier(0);
-
-  float hr[16], hi[16], yr[16], yi[16];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    if (HRES == 0) {
-      hr[s] = fmaf(a, h1[s].x - h0[s].x, h0[s].x);
-      hi[s] = fmaf(a, h1[s].y - h0[s].y, h0[s].y);
-    } else {
-      hr[s] = h0[s].x;
-      hi[s] = h0[s].y;
+      const float2 v0 = b0[s * NL];
+      if (HRES == 0) {
+        const float2 v1 = b1[s * NL];
+        hr[s] = fmaf(a, v1.x - v0.x, v0.x);
+        hi[s] = fmaf(a, v1.y - v0.y, v0.y);
+      } else {
+        hr[s] = v0.x;
+        hi[s] = v0.y;
+      }
     }
   }
   if (nq < 4) {  // wave-uniform: only fewer than 64 antennas need masking
@@ -283,39 +302,24 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
       for (int s = 0; s < 16; ++s) hr[s] = hi[s] = 0.f;
     }
   }
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    yr[2 * i] = yv[i].x;
-    yi[2 * i] = yv[i].y;
-    yr[2 * i + 1] = yv[i].z;
-    yi[2 * i + 1] = yv[i].w;
-  }
 
-  // ---- 3. Gram and matched filter on the matrix cores -------------------------------------
-  // FP32: Z = H^H Y with three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
-  //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
-  // 16-bit inputs: four products, no cancellation on top of the input rounding.
+  // ---- 3. Gram on the matrix cores:  Re G = Hr^T Hr + Hi^T Hi,  P = Hr^T Hi --------------
   floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, z_r = acc_g, z_i = acc_g;
+  LowpH<half8> h16;
+  LowpH<bf16x8> hb16;
   if constexpr (PREC == kPrecF32) {
-    floatx4 acc_m1 = acc_g, acc_m2 = acc_g, acc_m3 = acc_g;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       acc_g = mfma(hr[s], hr[s], acc_g);
       acc_g = mfma(hi[s], hi[s], acc_g);
       acc_p = mfma(hr[s], hi[s], acc_p);
-      acc_m1 = mfma(hr[s], yr[s], acc_m1);
-      acc_m2 = mfma(hi[s], yi[s], acc_m2);
-      acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      z_r[v] = acc_m1[v] + acc_m2[v];
-      z_i[v] = acc_m3[v] - acc_m1[v] + acc_m2[v];
     }
   } else if constexpr (PREC == kPrecF16) {
-    gram_mf_lowp<half8, _Float16>(hr, hi, yr, yi, acc_g, acc_p, z_r, z_i);
+    h16 = pack_h<half8, _Float16>(hr, hi);
+    gram_lowp(h16, acc_g, acc_p);
   } else {
-    gram_mf_lowp<bf16x8, __bf16>(hr, hi, yr, yi, acc_g, acc_p, z_r, z_i);
+    hb16 = pack_h<bf16x8, __bf16>(hr, hi);
+    gram_lowp(hb16, acc_g, acc_p);
   }
 
   // ---- 4. G = Re + j (P - P^T) + s2 I, padded layers -> identity; invert in place ---------
@@ -345,8 +349,44 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
     ar[v] *= scale;
     ai[v] *= scale;
   }
+  // Keep the matched filter (the first use of the received samples) after the inversion.
+  __builtin_amdgcn_sched_barrier(0);
 
-  // ---- 5. X_hat = G^-1 Z on the matrix cores ---------------------------------------------
+  // ---- 5. matched filter Z = H^H Y on the matrix cores ------------------------------------
+  {
+    float yr[16], yi[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      yr[2 * i] = yv[i].x;
+      yi[2 * i] = yv[i].y;
+      yr[2 * i + 1] = yv[i].z;
+      yi[2 * i + 1] = yv[i].w;
+    }
+    if constexpr (PREC == kPrecF32) {
+      // Three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
+      //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
+      floatx4 acc_m1 = acc_g, acc_m2 = acc_g, acc_m3 = acc_g;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc_m1[v] = acc_m2[v] = acc_m3[v] = 0.f;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        acc_m1 = mfma(hr[s], yr[s], acc_m1);
+        acc_m2 = mfma(hi[s], yi[s], acc_m2);
+        acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        z_r[v] = acc_m1[v] + acc_m2[v];
+        z_i[v] = acc_m3[v] - acc_m1[v] + acc_m2[v];
+      }
+    } else if constexpr (PREC == kPrecF16) {
+      mf_lowp<half8, _Float16>(h16, yr, yi, z_r, z_i);
+    } else {
+      mf_lowp<bf16x8, __bf16>(hb16, yr, yi, z_r, z_i);
+    }
+  }
+
+  // ---- 6. X_hat = G^-1 Z on the matrix cores ---------------------------------------------
   // A[i = c][m = 4q + s] = G^-1[c][4q+s] = conj(G^-1[4q+s][c]) = (ar[s], -ai[s]);
   // B[m = 4q + s][d = c] = Z[4q+s][c].
   // Three real products again: Re = ar zr + ai zi,  Im = (ar - ai)(zr + zi) - ar zr + ai zi.
@@ -366,7 +406,7 @@ __global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __
     acc_xi[v] = acc_n3[v] - acc_n1[v] + acc_n2[v];
   }
 
-  // ---- 6. unbias and store: lane (q, d = c) holds layers 4q .. 4q+3 of data symbol d ------
+  // ---- 7. unbias and store: lane (q, d = c) holds layers 4q .. 4q+3 of data symbol d ------
   float dl[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
