@@ -197,13 +197,17 @@ __device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16])
 }
 
 template <int HRES, int NL, int PREC>
-__global__ void __launch_bounds__(256) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
                                                         const float* __restrict__ nvar,
                                                         float2* __restrict__ x,
                                                         float* __restrict__ nv) {
   __shared__ float lds_t[4][16 * 17];
-  __shared__ __attribute__((aligned(16))) float2 lds_h[4 * kMaxRx * NL];
+  // Channel rows staged per block: full resolution needs the 4 subcarriers' rows; at pilot
+  // resolution 9..16 layers imply comb 8 (Nl <= C T), whose 4 subcarriers span at most 3
+  // pilot rows, and 5..8 layers at most 4 (comb 4).
+  constexpr int kRows = (HRES == 1 || NL <= 8) ? 4 : 3;
+  __shared__ __attribute__((aligned(16))) float2 lds_h[kRows * kMaxRx * NL];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int q = lane >> 4;  // K group / accumulator row group
