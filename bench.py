@@ -1,7 +1,9 @@
 """Benchmark of the uplink receive hot path on one MI355X.
 
-A step is one pass of the whole path -- chest_ls -> mmse_detect -> llr_demap -- over one
-batch of synthetic slots already resident in HBM.  The default workload is 64 Rx x 16
+A step is one pass of the whole path -- channel estimation, detection, demapping -- over one
+batch of synthetic slots already resident in HBM: chest_ls -> mmse_llr (detection with the
+demapping in its epilogue) where the shape takes the matrix-core detector, else chest_ls ->
+mmse_detect -> llr_demap; the three-call chain is timed beside the fused one.  The default workload is 64 Rx x 16
 layers, 273 PRB (3276 subcarriers) x 14 symbols, 64QAM, one double-symbol DMRS occasion
 (comb 8, time cover 2), exponential-PDP TDL channel with 300 ns rms delay spread, SNR 0..30
 dB in 5 dB steps, 20 slots per SNR point: 140 slots, 39312 data REs each.
@@ -30,25 +32,34 @@ FP32_VALU_PEAK_TFLOPS = 78.6     # FP32 vector FMA without packed-FP32 instructi
 CMAC = 8  # real flops per complex multiply-accumulate
 
 PROFILES = os.path.join(ROOT, "profiles")
-DETECTOR_SOURCES = ("paper_2510_07843_amd/csrc/mmse_mfma.hip", "paper_2510_07843_amd/csrc/geom.h")
+KERNEL_SOURCES = {
+    "mmse_detect": ("paper_2510_07843_amd/csrc/mmse_mfma.hip", "paper_2510_07843_amd/csrc/geom.h",
+                    "paper_2510_07843_amd/csrc/llr_math.h"),
+    "mmse_llr": ("paper_2510_07843_amd/csrc/mmse_mfma.hip", "paper_2510_07843_amd/csrc/geom.h",
+                 "paper_2510_07843_amd/csrc/llr_math.h"),
+}
 
 
-def measured_traffic(tag: str):
-    """HBM bytes per mmse_detect launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary for this workload, or None when there is none or the detector's source has
-    changed since the counters were taken."""
+def source_digest(kernel: str) -> str:
     import hashlib
-    path = os.path.join(PROFILES, f"traffic_mmse_detect_{tag}.md")
-    if not os.path.exists(path):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, tag: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary for this workload, or None when there is none or the kernel's source has changed
+    since the counters were taken."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{tag}.md")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
         return None
     fields = dict(l.split(": ", 1) for l in open(path).read().splitlines()
-                  if l.startswith("mmse_detect_"))
-    h = hashlib.sha256()
-    for f in DETECTOR_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if fields.get("mmse_detect_source_sha256") != h.hexdigest():
+                  if l.startswith(kernel + "_"))
+    if fields.get(f"{kernel}_source_sha256") != source_digest(kernel):
         return None
-    return float(fields["mmse_detect_traffic_bytes_per_launch"])
+    return float(fields[f"{kernel}_traffic_bytes_per_launch"])
 
 
 def algorithmic_costs(shape, h_res=0):
@@ -73,7 +84,15 @@ def algorithmic_costs(shape, h_res=0):
         bytes=re * NR * 8 + h_bytes + S * 4 + re * NL * 8 + re * NL * 4,
         flops=CMAC * (S * nsc * n_gram * (gram_per_sc + chol_per_sc) + re * per_re))
     llr = dict(bytes=re * NL * (8 + 4) + re * NL * Q * 4, flops=re * NL * Q * 6)
-    return dict(chest_ls=chest, mmse_detect=mmse, llr_demap=llr, data_re=re)
+    fused = dict(bytes=mmse["bytes"] - re * NL * (8 + 4) + re * NL * Q * 4,
+                 flops=mmse["flops"] + llr["flops"])
+    return dict(chest_ls=chest, mmse_detect=mmse, llr_demap=llr, mmse_llr=fused, data_re=re)
+
+
+def fused_eligible(shape) -> bool:
+    """Shapes the matrix-core detector (and so the fused detection + demapping) takes."""
+    return (shape.n_occ == 1 and 5 <= shape.n_layers <= 16 and shape.n_rx % 16 == 0
+            and shape.n_rx <= 64 and shape.n_dsym <= 16)
 
 
 def cpu_baseline(b, budget_s: float):
@@ -142,6 +161,8 @@ def main():
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="input precision of the detector's Gram and matched filter")
+    ap.add_argument("--path", default="auto", choices=["auto", "fused", "separate"],
+                    help="fused detection + demapping (matrix-core shapes) or three calls")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
@@ -188,25 +209,31 @@ def main():
     llr = torch.empty(ranphy.buffer_floats(shape, ranphy.BUF_LLR), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
-    names = ("chest_ls", "mmse_detect", "llr_demap")
+    fused = fused_eligible(shape) if args.path == "auto" else args.path == "fused"
 
-    def run_timed(precision):
+    def run_timed(precision, fused):
         """Warm up, then time exactly args.steps steps; returns (ms per step, per-kernel ms)."""
+        names = ("chest_ls", "mmse_llr") if fused else ("chest_ls", "mmse_detect", "llr_demap")
         ev = {n: [] for n in names}
 
         def step(record):
-            marks = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+            marks = ([torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+                     if record else None)
             if record:
                 marks[0].record()
             ranphy.chest_ls(shape, rx, pil, h=h, h_res=h_res)
             if record:
                 marks[1].record()
-            ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv, precision=precision)
+            if fused:
+                ranphy.mmse_llr(shape, rx, h, nvar, h_res=h_res, llr=llr, precision=precision)
+            else:
+                ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv,
+                                   precision=precision)
+                if record:
+                    marks[2].record()
+                ranphy.llr_demap(shape, x, nv, llr=llr)
             if record:
-                marks[2].record()
-            ranphy.llr_demap(shape, x, nv, llr=llr)
-            if record:
-                marks[3].record()
+                marks[-1].record()
                 for i, n in enumerate(names):
                     ev[n].append((marks[i], marks[i + 1]))
 
@@ -223,7 +250,8 @@ def main():
         return (t_start.elapsed_time(t_end) / args.steps,
                 {n: float(np.mean([a.elapsed_time(c) for a, c in ev[n]])) for n in names})
 
-    ms_step, kern_ms = run_timed(prec)
+    ms_step, kern_ms = run_timed(prec, fused)
+    names = tuple(kern_ms)
 
     costs = algorithmic_costs(shape, h_res)
     re = costs["data_re"]
@@ -232,19 +260,20 @@ def main():
     # Dominant kernel and its bound: time at the HBM roof vs at the compute roof.
     dom = max(names, key=lambda n: kern_ms[n])
     c = costs[dom]
-    compute_peak = FP32_MFMA_PEAK_TFLOPS if dom == "mmse_detect" else FP32_VALU_PEAK_TFLOPS
+    on_mfma = dom in ("mmse_detect", "mmse_llr")
+    compute_peak = FP32_MFMA_PEAK_TFLOPS if on_mfma else FP32_VALU_PEAK_TFLOPS
     t_bytes = c["bytes"] / (HBM_PEAK_GBS * 1e9)
     t_flops = c["flops"] / (compute_peak * 1e12)
     sec = kern_ms[dom] * 1e-3
     if t_bytes >= t_flops:
         roof = dict(bound="hbm", achieved=c["bytes"] / sec / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
     else:
-        roof = dict(bound="mfma" if dom == "mmse_detect" else "alu",
+        roof = dict(bound="mfma" if on_mfma else "alu",
                     achieved=c["flops"] / sec / 1e12, peak=compute_peak, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = dom
     tag = f"{shape.n_rx}x{shape.n_layers}_{shape.n_slots}slots"
-    roof["traffic"] = (measured_traffic(tag) if (dom == "mmse_detect" and h_res == ranphy.H_PILOT)
+    roof["traffic"] = (measured_traffic(dom, tag) if (h_res == ranphy.H_PILOT and prec == ranphy.PREC_FP32)
                        else None)
     roof["algorithmic_bytes"] = c["bytes"]
     roof["algorithmic_flops"] = c["flops"]
@@ -259,7 +288,8 @@ def main():
                                f"symbols, qm={shape.qm}, DMRS comb {shape.dmrs_comb} x TD {shape.dmrs_td}, "
                                f"{shape.n_slots} slots, h_res={args.h_res}, detector {args.prec}",
                    "slots": shape.n_slots, "data_re_per_step": re,
-                   "path": "plain_fp32" if args.prec == "fp32" else f"mixed_{args.prec}"},
+                   "path": ("plain_fp32" if args.prec == "fp32" else f"mixed_{args.prec}")
+                           + ("_fused" if fused else "_separate")},
         "kernels_ms": kern_ms,
         "roofline": roof,
     }
@@ -271,22 +301,25 @@ def main():
             "bytes_per_launch": cc["bytes"], "flops_per_launch": cc["flops"]}
     if args.workload == "m" and h_res == ranphy.H_PILOT and not args.no_variants:
         variants = {}
+        quality = detection_quality(torch, ranphy, synth)
         for name, p in (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16),
                         ("bf16", ranphy.PREC_BF16)):
-            if name == args.prec:
-                v_ms, v_k = ms_step, kern_ms
-            else:
-                v_ms, v_k = run_timed(p)
-            variants[name] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
-                              "mmse_detect_ms": v_k["mmse_detect"]}
-        quality = detection_quality(torch, ranphy, synth)
-        for name in variants:
-            variants[name].update(quality[name])
+            for fz in (True, False):
+                key = name + ("" if fz else "_separate")
+                if p == prec and fz == fused:
+                    v_ms, v_k = ms_step, kern_ms
+                else:
+                    v_ms, v_k = run_timed(p, fz)
+                variants[key] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
+                                 "kernels_ms": v_k}
+                variants[key].update(quality[name])
         out["variants"] = variants
         out["variants_note"] = ("Gram and matched filter with FP32 / FP16 / BF16 inputs (FP32 "
-                                "accumulation, FP32 inversion); SINR = E|x|^2 / E|x~ - x|^2 "
-                                "against the transmitted symbols on one slot per SNR point "
-                                "(0..30 dB), loss relative to the FP64 oracle on the same slots")
+                                "accumulation, FP32 inversion), demapping fused into the "
+                                "detector or (_separate) as its own pass; SINR = E|x|^2 / "
+                                "E|x~ - x|^2 against the transmitted symbols on one slot per "
+                                "SNR point (0..30 dB), loss relative to the FP64 oracle on the "
+                                "same slots")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_budget)
     print(json.dumps(out), flush=True)

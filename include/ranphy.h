@@ -158,6 +158,19 @@ RANPHY_API int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* r
                                        float* x, float* nv, int precision, void* stream);
 
 /*
+ * Detection and demapping in one pass: ranphy_mmse_detect_prec followed by ranphy_llr_demap,
+ * with the demapping done by the detector as it produces each symbol, so the symbols and
+ * variances need not travel through HBM.  x and nv are optional outputs: both NULL (only
+ * LLRs are written) or both given (written exactly as ranphy_mmse_detect_prec writes them).
+ * Same shapes as the reduced-precision modes (one DMRS occasion, 5..16 layers, n_rx a
+ * multiple of 16, every buffer 16-byte aligned); others return RANPHY_ERR_UNSUPPORTED.
+ *   llr  out [slot][dsym][sc][layer][qm] float, as ranphy_llr_demap.
+ */
+RANPHY_API int ranphy_mmse_llr(const ranphy_slot_desc* d, const float* rx, const float* h,
+                               int h_res, const float* noise_var, float* x, float* nv,
+                               float* llr, int precision, void* stream);
+
+/*
  * Max-log LLRs of Gray square QAM (3GPP NR mapping structure: bits b0, b2, .. on the
  * in-phase axis, b1, b3, .. on the quadrature axis), unit average energy:
  *   llr_b = (min_{s: b=1} |x - s|^2 - min_{s: b=0} |x - s|^2) / nv,  positive favours 0.

@@ -32,7 +32,8 @@ BUF_RX, BUF_PILOTS, BUF_H, BUF_NOISE_VAR, BUF_X, BUF_NV, BUF_LLR = range(7)
 
 EXPORTED_SYMBOLS = (
     "ranphy_abi_version", "ranphy_status_str", "ranphy_buffer_floats",
-    "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_llr_demap",
+    "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_mmse_llr",
+    "ranphy_llr_demap",
 )
 
 
@@ -87,9 +88,10 @@ def lib() -> ctypes.CDLL:
         L.ranphy_chest_ls.argtypes = [D, P, P, P, ctypes.c_int, P]
         L.ranphy_mmse_detect.argtypes = [D, P, P, ctypes.c_int, P, P, P, P]
         L.ranphy_mmse_detect_prec.argtypes = [D, P, P, ctypes.c_int, P, P, P, ctypes.c_int, P]
+        L.ranphy_mmse_llr.argtypes = [D, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
         L.ranphy_llr_demap.argtypes = [D, P, P, P, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
-                  "ranphy_llr_demap"):
+                  "ranphy_mmse_llr", "ranphy_llr_demap"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -182,6 +184,29 @@ def mmse_detect(shape, rx: torch.Tensor, h: torch.Tensor, noise_var: torch.Tenso
                                            _stream(stream))
     _check("ranphy_mmse_detect", st)
     return x, nv
+
+
+def mmse_llr(shape, rx: torch.Tensor, h: torch.Tensor, noise_var: torch.Tensor,
+             h_res: int = H_PILOT, llr: Optional[torch.Tensor] = None,
+             x: Optional[torch.Tensor] = None, nv: Optional[torch.Tensor] = None,
+             precision: int = PREC_FP32, stream=None) -> torch.Tensor:
+    """Detection and max-log demapping in one pass; returns the LLRs.  ``x`` and ``nv``
+    (both or neither) also receive the equalised symbols and variances."""
+    d = desc_of(shape)
+    nl = buffer_floats(d, BUF_LLR)
+    if llr is None:
+        llr = torch.empty(nl, dtype=torch.float32, device=rx.device)
+    if (x is None) != (nv is None):
+        raise ValueError("x and nv are given together or not at all")
+    args = (_as_dev(rx, "rx", torch.complex64, buffer_floats(d, BUF_RX)),
+            _as_dev(h, "h", torch.complex64, buffer_floats(d, BUF_H, h_res)))
+    pn = _as_dev(noise_var, "noise_var", torch.float32, buffer_floats(d, BUF_NOISE_VAR))
+    px = None if x is None else _as_dev(x, "x", torch.complex64, buffer_floats(d, BUF_X))
+    pv = None if nv is None else _as_dev(nv, "nv", torch.float32, buffer_floats(d, BUF_NV))
+    pl = _as_dev(llr, "llr", torch.float32, nl)
+    _check("ranphy_mmse_llr", lib().ranphy_mmse_llr(ctypes.byref(d), *args, h_res, pn, px, pv, pl,
+                                                    precision, _stream(stream)))
+    return llr
 
 
 def llr_demap(shape, x: torch.Tensor, nv: torch.Tensor, llr: Optional[torch.Tensor] = None,

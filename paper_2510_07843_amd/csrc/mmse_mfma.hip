@@ -31,6 +31,7 @@
 #include <float.h>
 
 #include "geom.h"
+#include "llr_math.h"
 
 namespace ranphy {
 namespace {
@@ -196,12 +197,36 @@ __device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16])
   }
 }
 
+// Max-log LLRs of the 4 layers 4q .. 4q+3 a lane holds, written to their 4 Qm contiguous
+// floats (16-byte stores when all 4 layers exist; llr 16-byte aligned).
+template <int QM, int NL>
+__device__ __forceinline__ void store_llr(float* __restrict__ dst, const float (&xo)[8],
+                                          const float (&vo)[4], int q) {
+  float out[4 * QM];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) llr_one<QM>(make_float2(xo[2 * v], xo[2 * v + 1]), vo[v], out + v * QM);
+  if (NL % 4 == 0) {
+    float4* __restrict__ d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+    for (int i = 0; i < QM; ++i)
+      d4[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (4 * q + v < NL) {
+#pragma unroll
+        for (int b = 0; b < QM; ++b) dst[v * QM + b] = out[v * QM + b];
+      }
+  }
+}
+
 template <int HRES, int NL, int PREC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
                                                         const float* __restrict__ nvar,
                                                         float2* __restrict__ x,
-                                                        float* __restrict__ nv) {
+                                                        float* __restrict__ nv,
+                                                        float* __restrict__ llr) {
   __shared__ float lds_t[4][16 * 17];
   // Channel rows staged per block: full resolution needs the 4 subcarriers' rows; at pilot
   // resolution 9..16 layers imply comb 8 (Nl <= C T), whose 4 subcarriers span at most 3
@@ -415,7 +440,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 #pragma unroll
   for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
   const int d = c;
-  if (live && d < ND) {
+  if (live && d < ND && 4 * q < NL) {
     const int64_t o = ((int64_t)(slot * ND + d) * g.n_sc + k) * NL;
     float xo[8], vo[4];
 #pragma unroll
@@ -426,20 +451,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
       xo[2 * v + 1] = ok ? acc_xi[v] * im : __builtin_nanf("");
       vo[v] = ok ? sd * im : __builtin_inff();
     }
-    if (NL % 4 == 0) {  // layers 4q .. 4q+3 are 32 contiguous bytes of x, 16 of nv
-      if (4 * q >= NL) return;  // lane groups of padded layers store nothing
-      float4* __restrict__ xd = reinterpret_cast<float4*>(x + o + 4 * q);
-      xd[0] = make_float4(xo[0], xo[1], xo[2], xo[3]);
-      xd[1] = make_float4(xo[4], xo[5], xo[6], xo[7]);
-      *reinterpret_cast<float4*>(nv + o + 4 * q) = make_float4(vo[0], vo[1], vo[2], vo[3]);
-    } else {
+    // Layers 4q .. 4q+3 of one RE: 32 contiguous bytes of x, 16 of nv, 16 Qm of LLRs.
+    if (x != nullptr) {
+      if (NL % 4 == 0) {
+        float4* __restrict__ xd = reinterpret_cast<float4*>(x + o + 4 * q);
+        xd[0] = make_float4(xo[0], xo[1], xo[2], xo[3]);
+        xd[1] = make_float4(xo[4], xo[5], xo[6], xo[7]);
+        *reinterpret_cast<float4*>(nv + o + 4 * q) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+      } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int l = 4 * q + v;
-        if (l < NL) {
-          x[o + l] = make_float2(xo[2 * v], xo[2 * v + 1]);
-          nv[o + l] = vo[v];
+        for (int v = 0; v < 4; ++v) {
+          if (4 * q + v < NL) {
+            x[o + 4 * q + v] = make_float2(xo[2 * v], xo[2 * v + 1]);
+            nv[o + 4 * q + v] = vo[v];
+          }
         }
+      }
+    }
+    if (llr != nullptr) {  // demapping fused into the detector (qm is wave-uniform)
+      switch (g.qm) {
+        case 2: store_llr<2, NL>(llr + (o + 4 * q) * 2, xo, vo, q); break;
+        case 4: store_llr<4, NL>(llr + (o + 4 * q) * 4, xo, vo, q); break;
+        case 6: store_llr<6, NL>(llr + (o + 4 * q) * 6, xo, vo, q); break;
+        default: store_llr<8, NL>(llr + (o + 4 * q) * 8, xo, vo, q); break;
       }
     }
   }
@@ -447,57 +481,59 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 
 template <int HRES, int NL, int PREC>
 void launch_one(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
-                float2* x, float* nv, hipStream_t s) {
+                float2* x, float* nv, float* llr, hipStream_t s) {
   hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC>), grid, dim3(256), 0, s, g, rx, h, nvar,
-                     x, nv);
+                     x, nv, llr);
 }
 
 template <int HRES, int PREC>
 void launch_nl(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
-               float2* x, float* nv, hipStream_t s) {
+               float2* x, float* nv, float* llr, hipStream_t s) {
   switch (g.n_layers) {
-    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
-    default: launch_one<HRES, 16, PREC>(g, grid, rx, h, nvar, x, nv, s); break;
+    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    default: launch_one<HRES, 16, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
   }
 }
 
 template <int PREC>
 void launch_prec(const Geom& g, dim3 grid, const float2* rx, const float2* h, int h_res,
-                 const float* nvar, float2* x, float* nv, hipStream_t s) {
-  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, h, nvar, x, nv, s);
-  else launch_nl<1, PREC>(g, grid, rx, h, nvar, x, nv, s);
+                 const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
+  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, h, nvar, x, nv, llr, s);
+  else launch_nl<1, PREC>(g, grid, rx, h, nvar, x, nv, llr, s);
 }
 
 }  // namespace
 
 bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
-                        const void* nv) {
+                        const void* nv, const void* llr) {
   // 16-byte aligned buffers: 16-byte loads of the received grid and channel rows, 16-byte
-  // stores of x and nv.
-  const uintptr_t mis = ((uintptr_t)rx | (uintptr_t)h | (uintptr_t)x | (uintptr_t)nv) & 15u;
+  // stores of x, nv and LLRs (absent outputs are NULL, which is aligned).
+  const uintptr_t mis =
+      ((uintptr_t)rx | (uintptr_t)h | (uintptr_t)x | (uintptr_t)nv | (uintptr_t)llr) & 15u;
   return mis == 0 && g.n_occ == 1 && g.n_layers >= 5 && g.n_layers <= 16 &&
          g.n_rx % 16 == 0 && g.n_rx <= 64 && g.n_dsym <= 16;
 }
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
-                            const float* nvar, float2* x, float* nv, int prec, hipStream_t s) {
+                            const float* nvar, float2* x, float* nv, float* llr, int prec,
+                            hipStream_t s) {
   const int64_t waves = (int64_t)g.n_slots * g.n_sc;
   const int64_t blocks = (waves + 3) / 4;
   const dim3 grid((unsigned)((blocks + kXcds - 1) / kXcds * kXcds));
   switch (prec) {
-    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, h, h_res, nvar, x, nv, s); break;
-    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, h, h_res, nvar, x, nv, s); break;
-    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, h, h_res, nvar, x, nv, s); break;
+    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, h, h_res, nvar, x, nv, llr, s); break;
+    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, h, h_res, nvar, x, nv, llr, s); break;
+    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, h, h_res, nvar, x, nv, llr, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

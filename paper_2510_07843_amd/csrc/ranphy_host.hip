@@ -11,10 +11,10 @@
 namespace ranphy {
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
-                            const float* noise_var, float2* x, float* nv, int prec,
+                            const float* noise_var, float2* x, float* nv, float* llr, int prec,
                             hipStream_t s);
 bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
-                        const void* nv);
+                        const void* nv, const void* llr);
 
 namespace {
 
@@ -160,17 +160,40 @@ int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx, const fl
   const float2* h2 = reinterpret_cast<const float2*>(h);
   float2* x2 = reinterpret_cast<float2*>(x);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool mfma = ranphy::mmse_mfma_eligible(g, rx, h, x, nv);
+  const bool mfma = ranphy::mmse_mfma_eligible(g, rx, h, x, nv, nullptr);
   if (precision != RANPHY_PREC_FP32 && !mfma) return RANPHY_ERR_UNSUPPORTED;
   if (mfma)
     return ranphy::status_of(
-        ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, precision, s));
+        ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, nullptr, precision, s));
   return ranphy::status_of(ranphy::launch_mmse_re(g, rx2, h2, h_res, noise_var, x2, nv, s));
 }
 
 int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
                        const float* noise_var, float* x, float* nv, void* stream) {
   return ranphy_mmse_detect_prec(d, rx, h, h_res, noise_var, x, nv, RANPHY_PREC_FP32, stream);
+}
+
+int ranphy_mmse_llr(const ranphy_slot_desc* d, const float* rx, const float* h, int h_res,
+                    const float* noise_var, float* x, float* nv, float* llr, int precision,
+                    void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+  if (precision != RANPHY_PREC_FP32 && precision != RANPHY_PREC_FP16 &&
+      precision != RANPHY_PREC_BF16)
+    return RANPHY_ERR_INVALID;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if ((x == nullptr) != (nv == nullptr)) return RANPHY_ERR_INVALID;
+  if (!ranphy::aligned8(rx) || !ranphy::aligned8(h) || !ranphy::aligned8(llr) ||
+      (x != nullptr && (!ranphy::aligned8(x) || !ranphy::aligned8(nv))) ||
+      noise_var == nullptr || ((uintptr_t)noise_var & 3u))
+    return RANPHY_ERR_INVALID;
+  if (!ranphy::mmse_mfma_eligible(g, rx, h, x, nv, llr)) return RANPHY_ERR_UNSUPPORTED;
+  return ranphy::status_of(ranphy::launch_mmse_mfma(
+      g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(h), h_res,
+      noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
+      static_cast<hipStream_t>(stream)));
 }
 
 int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const float* nv, float* llr,

@@ -95,6 +95,7 @@ def _calls(L, d, p):
         L.ranphy_chest_ls(ctypes.byref(d), P(p), P(p), P(p), 0, None),
         L.ranphy_mmse_detect(ctypes.byref(d), P(p), P(p), 0, P(p), P(p), P(p), None),
         L.ranphy_llr_demap(ctypes.byref(d), P(p), P(p), P(p), None),
+        L.ranphy_mmse_llr(ctypes.byref(d), P(p), P(p), 0, P(p), P(p), P(p), P(p), 0, None),
     ]
 
 
@@ -102,7 +103,7 @@ def _calls(L, d, p):
 def test_invalid_descriptors_rejected_before_launch(L, kw, code):
     d = _desc(**kw)
     # Pointers that would fault if touched; validation must stop first.
-    assert _calls(L, d, 0x1000) == [code] * 3
+    assert _calls(L, d, 0x1000) == [code] * 4
     assert L.ranphy_buffer_floats(ctypes.byref(d), ranphy.BUF_RX, 0) == code
 
 
@@ -115,8 +116,8 @@ def test_null_descriptor(L):
 
 def test_null_and_misaligned_pointers_rejected(L):
     d = _desc()
-    assert _calls(L, d, 0) == [-1] * 3
-    assert _calls(L, d, 0x1004) == [-1] * 3
+    assert _calls(L, d, 0) == [-1] * 4
+    assert _calls(L, d, 0x1004) == [-1] * 4
     P = ctypes.c_void_p
     assert L.ranphy_chest_ls(ctypes.byref(d), P(8), P(8), P(8), 2, None) == -1  # bad h_res
     assert L.ranphy_mmse_detect(ctypes.byref(d), P(8), P(8), 5, P(8), P(8), P(8), None) == -1
@@ -124,7 +125,7 @@ def test_null_and_misaligned_pointers_rejected(L):
 
 def test_empty_batch_is_a_no_op(L):
     d = _desc(n_slots=0)
-    assert _calls(L, d, 0) == [0] * 3
+    assert _calls(L, d, 0) == [0] * 4
 
 
 def test_binding_refuses_host_tensors(L):
@@ -150,3 +151,26 @@ def test_reduced_precision_rejected_off_the_matrix_core_shapes(L):
     # Unknown precision code.
     assert L.ranphy_mmse_detect_prec(ctypes.byref(d), P(0x1000), P(0x1000), 0, P(0x1000),
                                      P(0x1000), P(0x1000), 7, None) == -1
+
+
+def test_fused_detect_demap_validation(L):
+    P = ctypes.c_void_p
+    # Matrix-core shape: 16 Rx, 8 layers, one occasion.
+    d = _desc(n_rx=16, n_layers=8, dmrs_comb=4, dmrs_td=2)
+    a = P(0x1000)
+    # x and nv come together or not at all.
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 0, a, a, None, a, 0, None) == -1
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 0, a, None, a, a, 0, None) == -1
+    # The LLR buffer is required; the noise variances are required.
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 0, a, None, None, None, 0, None) == -1
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 0, None, None, None, a, 0, None) == -1
+    # Unknown precision or channel resolution.
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 0, a, None, None, a, 5, None) == -1
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 3, a, None, None, a, 0, None) == -1
+    # 8-byte but not 16-byte aligned LLR buffer: the fused path needs 16-byte stores.
+    assert L.ranphy_mmse_llr(ctypes.byref(d), a, a, 0, a, None, None, P(0x1008), 0, None) == -2
+    # Off the matrix-core shapes: two DMRS occasions, or four layers.
+    d2 = _desc(n_rx=16, n_layers=8, dmrs_comb=4, dmrs_td=2, dmrs_sym0=(2, 10))
+    assert L.ranphy_mmse_llr(ctypes.byref(d2), a, a, 0, a, None, None, a, 0, None) == -2
+    d3 = _desc(n_rx=16, n_layers=4)
+    assert L.ranphy_mmse_llr(ctypes.byref(d3), a, a, 0, a, a, a, a, 1, None) == -2

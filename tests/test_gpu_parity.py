@@ -355,6 +355,64 @@ def test_reduced_precision_sinr_loss_64x16():
         say("; ".join(line))
 
 
+FUSED = ["m", "prb5_l9_r32", "prb3_l12_r48", "prb2_l5_r16", "prb4_l8_short",
+         "prb1_l16_dmrs_end"]
+
+
+@pytest.mark.parametrize("name", FUSED)
+@pytest.mark.parametrize("h_res", [ranphy.H_PILOT, ranphy.H_FULL])
+def test_fused_detect_demap(name, h_res):
+    # Detection with the demapping in its epilogue: x and nv identical to the detector's,
+    # LLRs within the per-call bar of llr_demap on those x and nv and of the oracle's
+    # demapping of them, and the LLR-only mode identical to the mode that also writes x, nv.
+    shape = SHAPES[name]
+    say(f"mmse_llr {name} h_res={h_res}")
+    rx, pil, nvar, *_ = make_inputs(shape, 4, snr_db=18.0)
+    h = oracle.chest_ls(shape, rx, pil, h_res).astype(np.complex64)
+    rxd, hd, nd = dev(rx), dev(h), dev(nvar)
+    x1, v1 = ranphy.mmse_detect(shape, rxd, hd, nd, h_res=h_res)
+    x2 = torch.empty_like(x1)
+    v2 = torch.empty_like(v1)
+    l2 = ranphy.mmse_llr(shape, rxd, hd, nd, h_res=h_res, x=x2, nv=v2)
+    l3 = ranphy.mmse_llr(shape, rxd, hd, nd, h_res=h_res)
+    ls = ranphy.llr_demap(shape, x1, v1)
+    torch.cuda.synchronize()
+    assert x1.cpu().numpy().tobytes() == x2.cpu().numpy().tobytes()
+    assert v1.cpu().numpy().tobytes() == v2.cpu().numpy().tobytes()
+    assert l2.cpu().numpy().tobytes() == l3.cpu().numpy().tobytes()
+    lq = out_shape(shape) + (shape.qm,)
+    lg, lsep = host(l2, lq), host(ls, lq)
+    assert llr_tol_ok(lg, lsep).all()
+    lr = oracle.llr_demap(shape, host(x2, out_shape(shape)), host(v2, out_shape(shape)))
+    assert llr_tol_ok(lg, lr).all()
+    # Against the FP64 chain on the same channel estimate.
+    xr, nvr = oracle.mmse_detect(shape, rx, h, h_res, nvar)
+    lr64 = oracle.llr_demap(shape, xr.astype(np.complex64), nvr.astype(np.float32))
+    ok = check_end_to_end(shape, host(x2, out_shape(shape)), lg, xr, lr64)
+    assert (~ok).mean() < 1e-3
+
+
+@pytest.mark.parametrize("prec", [ranphy.PREC_FP16, ranphy.PREC_BF16])
+def test_fused_detect_demap_reduced_precision(prec):
+    shape = SHAPES["prb5_l9_r32"]
+    rx, pil, nvar, *_ = make_inputs(shape, 6, snr_db=20.0)
+    h = oracle.chest_ls(shape, rx, pil, ranphy.H_PILOT).astype(np.complex64)
+    rxd, hd, nd = dev(rx), dev(h), dev(nvar)
+    x1, v1 = ranphy.mmse_detect(shape, rxd, hd, nd, precision=prec)
+    lf = ranphy.mmse_llr(shape, rxd, hd, nd, precision=prec)
+    ls = ranphy.llr_demap(shape, x1, v1)
+    lq = out_shape(shape) + (shape.qm,)
+    assert llr_tol_ok(host(lf, lq), host(ls, lq)).all()
+
+
+def test_fused_detect_demap_empty_batch():
+    shape = M.with_slots(0)
+    e = torch.empty(0, dtype=torch.complex64, device="cuda")
+    ef = torch.empty(0, dtype=torch.float32, device="cuda")
+    ranphy.mmse_llr(shape, e, e, ef, llr=ef)
+    torch.cuda.synchronize()
+
+
 def test_llr_demap_8_byte_aligned_buffers():
     # Buffers 8- but not 16-byte aligned take the one-element-per-thread kernel.
     qm = 6
