@@ -17,8 +17,10 @@
 
 namespace ranphy {
 
+// The sign of each LLR is the sign of t_i.  Where t_i is zero (u on that bit's boundary) the
+// numerator is zero too, so the sign of zero never matters.
 template <int M>
-__device__ __forceinline__ void axis_llr(float u, float* out /* stride 2 */) {
+__device__ __forceinline__ void axis_llr(float u, float inv, float* out /* stride 2 */) {
   constexpr float lim = (float)((1 << M) - 1);
   float a = 2.f * floorf(0.5f * u) + 1.f;
   a = fminf(fmaxf(a, -lim), lim);
@@ -29,21 +31,21 @@ __device__ __forceinline__ void axis_llr(float u, float* out /* stride 2 */) {
   for (int i = 0; i < M; ++i) {
     if (i > 0) t = (float)(1 << (M - i)) - fabsf(t);
     const float dd = fabsf(t) + 1.f;
-    const float num = dd * dd - e2;
-    out[2 * i] = (t >= 0.f) ? num : -num;
+    out[2 * i] = copysignf(fmaf(dd, dd, -e2) * inv, t);
   }
 }
 
+// 1 / (scale^2 nv) by the hardware reciprocal (1 ulp): the LLRs carry the relative error of
+// the variance estimate, orders of magnitude above it.  nv = 0 gives infinite LLRs and an
+// infinite nv zero ones, as exact division would.
 template <int QM>
 __device__ __forceinline__ void llr_one(float2 v, float nvv, float* out) {
   constexpr int M = QM / 2;
   constexpr float sc2 = 2.f * (float)((1 << QM) - 1) / 3.f;  // scale^2
-  const float scale = sqrtf(sc2);
-  const float inv = 1.f / (sc2 * nvv);
-  axis_llr<M>(v.x * scale, out);
-  axis_llr<M>(v.y * scale, out + 1);
-#pragma unroll
-  for (int b = 0; b < QM; ++b) out[b] *= inv;
+  const float scale = __builtin_sqrtf(sc2);
+  const float inv = __builtin_amdgcn_rcpf(sc2 * nvv);
+  axis_llr<M>(v.x * scale, inv, out);
+  axis_llr<M>(v.y * scale, inv, out + 1);
 }
 
 }  // namespace ranphy

@@ -30,6 +30,8 @@
 //   each lane's 16 samples of one symbol are contiguous in memory.
 #include <float.h>
 
+#include <type_traits>
+
 #include "geom.h"
 #include "llr_math.h"
 
@@ -200,11 +202,8 @@ __device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16])
 // Max-log LLRs of the 4 layers 4q .. 4q+3 a lane holds, written to their 4 Qm contiguous
 // floats (16-byte stores when all 4 layers exist; llr 16-byte aligned).
 template <int QM, int NL>
-__device__ __forceinline__ void store_llr(float* __restrict__ dst, const float (&xo)[8],
-                                          const float (&vo)[4], int q) {
-  float out[4 * QM];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) llr_one<QM>(make_float2(xo[2 * v], xo[2 * v + 1]), vo[v], out + v * QM);
+__device__ __forceinline__ void store_llr(float* __restrict__ dst, const float (&out)[4 * QM],
+                                          int q) {
   if (NL % 4 == 0) {
     float4* __restrict__ d4 = reinterpret_cast<float4*>(dst);
 #pragma unroll
@@ -217,6 +216,62 @@ __device__ __forceinline__ void store_llr(float* __restrict__ dst, const float (
 #pragma unroll
         for (int b = 0; b < QM; ++b) dst[v * QM + b] = out[v * QM + b];
       }
+  }
+}
+
+// The fused demapping epilogue.  Lane (q, d) computes the LLRs of layers 4q .. 4q+3 of data
+// symbol d; the Nl Qm LLRs of one RE are contiguous in the output, and the wave's ND REs are
+// n_sc Nl Qm floats apart.  Written straight from the lanes, each store instruction touches
+// 64 scattered 16-byte pieces.  With kStaged the wave instead stages its ND x Nl Qm block in
+// LDS (its quarter of the channel-row buffer, free once every wave of the block is past the
+// channel reads) and writes it back with consecutive lanes on consecutive 16-byte (8-byte
+// when Nl Qm is not a multiple of 4) pieces of each RE's run; blocks whose ND x Nl Qm block
+// does not fit their quarter store straight from the lanes.  Staging pays off where the
+// detector itself is short (16-bit Gram and matched filter); with the FP32 products the
+// extra LDS round trip and barrier cost more than the scattered stores (measured).  Called
+// by every lane of the block (the barrier), with block-uniform qm, ND and live.
+template <int QM, int NL, int kStage, bool kStaged>
+__device__ __forceinline__ void emit_llr(float* __restrict__ llr, float* stage, int64_t seg0,
+                                         int64_t dstride, int64_t o, const float (&xo)[8],
+                                         const float (&vo)[4], int q, int d, int ND, bool mine,
+                                         bool live) {
+  float out[4 * QM];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) llr_one<QM>(make_float2(xo[2 * v], xo[2 * v + 1]), vo[v], out + v * QM);
+  constexpr int kRe = NL * QM;  // floats per RE
+  if (!kStaged || ND * kRe > kStage) {
+    if (mine) store_llr<QM, NL>(llr + (o + 4 * q) * QM, out, q);
+    return;
+  }
+  __syncthreads();  // every wave of the block is done with the channel rows
+  if (mine) {
+    float* dst = stage + d * kRe + 4 * q * QM;
+    if (kRe % 4 == 0) {
+#pragma unroll
+      for (int i = 0; i < QM; ++i)
+        if (NL % 4 == 0 || 4 * i < (NL - 4 * q) * QM)
+          reinterpret_cast<float4*>(dst)[i] =
+              make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2 * QM; ++i)
+        if (2 * i < (NL - 4 * q) * QM)
+          reinterpret_cast<float2*>(dst)[i] = make_float2(out[2 * i], out[2 * i + 1]);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!live) return;
+  // Lane L takes pieces L, L + 64, ..: piece f is piece f mod kCh of RE f / kCh.
+  using Piece = typename std::conditional<kRe % 4 == 0, float4, float2>::type;
+  constexpr int kW = sizeof(Piece) / sizeof(float);
+  constexpr int kCh = kRe / kW;  // pieces per RE
+  const int n = ND * kCh;
+  for (int f = d + 16 * q; f < n; f += 64) {
+    const int dd = f / kCh, m = f - dd * kCh;
+    reinterpret_cast<Piece*>(llr + (seg0 + dd * dstride) * QM)[m] =
+        reinterpret_cast<const Piece*>(stage)[f];
   }
 }
 
@@ -440,41 +495,45 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 #pragma unroll
   for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
   const int d = c;
-  if (live && d < ND && 4 * q < NL) {
-    const int64_t o = ((int64_t)(slot * ND + d) * g.n_sc + k) * NL;
-    float xo[8], vo[4];
+  const bool mine = live && d < ND && 4 * q < NL;
+  const int64_t o = ((int64_t)(slot * ND + (d < ND ? d : 0)) * g.n_sc + k) * NL;
+  float xo[8], vo[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float sd = s2 * dl[v];
-      const float im = __builtin_amdgcn_rcpf(1.f - sd);
-      xo[2 * v] = ok ? acc_xr[v] * im : __builtin_nanf("");
-      xo[2 * v + 1] = ok ? acc_xi[v] * im : __builtin_nanf("");
-      vo[v] = ok ? sd * im : __builtin_inff();
-    }
-    // Layers 4q .. 4q+3 of one RE: 32 contiguous bytes of x, 16 of nv, 16 Qm of LLRs.
-    if (x != nullptr) {
-      if (NL % 4 == 0) {
-        float4* __restrict__ xd = reinterpret_cast<float4*>(x + o + 4 * q);
-        xd[0] = make_float4(xo[0], xo[1], xo[2], xo[3]);
-        xd[1] = make_float4(xo[4], xo[5], xo[6], xo[7]);
-        *reinterpret_cast<float4*>(nv + o + 4 * q) = make_float4(vo[0], vo[1], vo[2], vo[3]);
-      } else {
+  for (int v = 0; v < 4; ++v) {
+    const float sd = s2 * dl[v];
+    const float im = __builtin_amdgcn_rcpf(1.f - sd);
+    xo[2 * v] = ok ? acc_xr[v] * im : __builtin_nanf("");
+    xo[2 * v + 1] = ok ? acc_xi[v] * im : __builtin_nanf("");
+    vo[v] = ok ? sd * im : __builtin_inff();
+  }
+  // Layers 4q .. 4q+3 of one RE: 32 contiguous bytes of x, 16 of nv.
+  if (mine && x != nullptr) {
+    if (NL % 4 == 0) {
+      float4* __restrict__ xd = reinterpret_cast<float4*>(x + o + 4 * q);
+      xd[0] = make_float4(xo[0], xo[1], xo[2], xo[3]);
+      xd[1] = make_float4(xo[4], xo[5], xo[6], xo[7]);
+      *reinterpret_cast<float4*>(nv + o + 4 * q) = make_float4(vo[0], vo[1], vo[2], vo[3]);
+    } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (4 * q + v < NL) {
-            x[o + 4 * q + v] = make_float2(xo[2 * v], xo[2 * v + 1]);
-            nv[o + 4 * q + v] = vo[v];
-          }
+      for (int v = 0; v < 4; ++v) {
+        if (4 * q + v < NL) {
+          x[o + 4 * q + v] = make_float2(xo[2 * v], xo[2 * v + 1]);
+          nv[o + 4 * q + v] = vo[v];
         }
       }
     }
-    if (llr != nullptr) {  // demapping fused into the detector (qm is wave-uniform)
-      switch (g.qm) {
-        case 2: store_llr<2, NL>(llr + (o + 4 * q) * 2, xo, vo, q); break;
-        case 4: store_llr<4, NL>(llr + (o + 4 * q) * 4, xo, vo, q); break;
-        case 6: store_llr<6, NL>(llr + (o + 4 * q) * 6, xo, vo, q); break;
-        default: store_llr<8, NL>(llr + (o + 4 * q) * 8, xo, vo, q); break;
-      }
+  }
+  if (llr != nullptr) {  // demapping fused into the detector (qm and the branch block-uniform)
+    constexpr int kStage = kRows * kMaxRx * NL / 2;  // floats: a quarter of lds_h
+    constexpr bool kStaged = PREC != kPrecF32;
+    float* stage = reinterpret_cast<float*>(lds_h) + wave * kStage;
+    const int64_t seg0 = ((int64_t)slot * ND * g.n_sc + k) * NL;  // RE (slot, d = 0, k)
+    const int64_t dstride = (int64_t)g.n_sc * NL;                  // REs between symbols
+    switch (g.qm) {
+      case 2: emit_llr<2, NL, kStage, kStaged>(llr, stage, seg0, dstride, o, xo, vo, q, c, ND, mine, live); break;
+      case 4: emit_llr<4, NL, kStage, kStaged>(llr, stage, seg0, dstride, o, xo, vo, q, c, ND, mine, live); break;
+      case 6: emit_llr<6, NL, kStage, kStaged>(llr, stage, seg0, dstride, o, xo, vo, q, c, ND, mine, live); break;
+      default: emit_llr<8, NL, kStage, kStaged>(llr, stage, seg0, dstride, o, xo, vo, q, c, ND, mine, live); break;
     }
   }
 }

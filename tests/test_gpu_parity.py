@@ -392,15 +392,27 @@ def test_fused_detect_demap(name, h_res):
     assert (~ok).mean() < 1e-3
 
 
+@pytest.mark.parametrize("name", FUSED)
+@pytest.mark.parametrize("h_res", [ranphy.H_PILOT, ranphy.H_FULL])
 @pytest.mark.parametrize("prec", [ranphy.PREC_FP16, ranphy.PREC_BF16])
-def test_fused_detect_demap_reduced_precision(prec):
-    shape = SHAPES["prb5_l9_r32"]
+def test_fused_detect_demap_reduced_precision(name, h_res, prec):
+    # The 16-bit modes stage the LLRs through LDS before storing them (16-byte pieces, or
+    # 8-byte ones where Nl Qm is not a multiple of 4: prb2_l5_r16); 16 layers of 256QAM over
+    # 12 data symbols fill a wave's staging area exactly (prb1_l16_dmrs_end).
+    shape = SHAPES[name]
+    say(f"mmse_llr {name} h_res={h_res} prec={prec}")
     rx, pil, nvar, *_ = make_inputs(shape, 6, snr_db=20.0)
-    h = oracle.chest_ls(shape, rx, pil, ranphy.H_PILOT).astype(np.complex64)
+    h = oracle.chest_ls(shape, rx, pil, h_res).astype(np.complex64)
     rxd, hd, nd = dev(rx), dev(h), dev(nvar)
-    x1, v1 = ranphy.mmse_detect(shape, rxd, hd, nd, precision=prec)
-    lf = ranphy.mmse_llr(shape, rxd, hd, nd, precision=prec)
+    x1, v1 = ranphy.mmse_detect(shape, rxd, hd, nd, h_res=h_res, precision=prec)
+    x2, v2 = torch.empty_like(x1), torch.empty_like(v1)
+    lf = ranphy.mmse_llr(shape, rxd, hd, nd, h_res=h_res, x=x2, nv=v2, precision=prec)
+    lo = ranphy.mmse_llr(shape, rxd, hd, nd, h_res=h_res, precision=prec)
     ls = ranphy.llr_demap(shape, x1, v1)
+    torch.cuda.synchronize()
+    assert x1.cpu().numpy().tobytes() == x2.cpu().numpy().tobytes()
+    assert v1.cpu().numpy().tobytes() == v2.cpu().numpy().tobytes()
+    assert lf.cpu().numpy().tobytes() == lo.cpu().numpy().tobytes()
     lq = out_shape(shape) + (shape.qm,)
     assert llr_tol_ok(host(lf, lq), host(ls, lq)).all()
 
