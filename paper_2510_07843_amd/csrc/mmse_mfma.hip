@@ -45,8 +45,18 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // Precision of the Gram and matched-filter products (inputs; accumulation is always FP32).
 enum { kPrecF32 = 0, kPrecF16 = 1, kPrecBF16 = 2 };
 
-constexpr float kPivotRel = 16.f * FLT_EPSILON;
 constexpr int kXcds = 8;
+// Condition estimate above which a subcarrier's system is solved again in FP64: the ratio
+// of the largest to the smallest elimination pivot, (max L_ii / min L_ii)^2 of the Gram's
+// Cholesky factor L.
+constexpr float kCondMax = 1e6f;
+
+// A pivot at or below this multiple of its original diagonal entry means the matrix is not
+// numerically positive definite in that precision.
+template <typename T>
+struct PivotRel;
+template <> struct PivotRel<float> { static constexpr float v = 16.f * FLT_EPSILON; };
+template <> struct PivotRel<double> { static constexpr double v = 16.0 * DBL_EPSILON; };
 
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -140,6 +150,28 @@ __device__ __forceinline__ float uniform_read(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// The same moves for FP64 values, one 32-bit half at a time.
+__device__ __forceinline__ int lo32(double v) { return (int)(unsigned)__double_as_longlong(v); }
+__device__ __forceinline__ int hi32(double v) { return (int)(__double_as_longlong(v) >> 32); }
+__device__ __forceinline__ double join64(int lo, int hi) {
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int SRC>
+__device__ __forceinline__ double row_bcast(double v) {
+  return join64(__builtin_amdgcn_mov_dpp(lo32(v), 0x150 + SRC, 0xF, 0xF, true),
+                __builtin_amdgcn_mov_dpp(hi32(v), 0x150 + SRC, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double lane_read(double v, int src_lane) {
+  return join64(__builtin_amdgcn_ds_bpermute(src_lane << 2, lo32(v)),
+                __builtin_amdgcn_ds_bpermute(src_lane << 2, hi32(v)));
+}
+__device__ __forceinline__ double uniform_read(double v, int lane) {
+  return join64(__builtin_amdgcn_readlane(lo32(v), lane), __builtin_amdgcn_readlane(hi32(v), lane));
+}
+
+__device__ __forceinline__ float recip(float p) { return __builtin_amdgcn_rcpf(p); }
+__device__ __forceinline__ double recip(double p) { return 1.0 / p; }
+
 // One Gauss-Jordan step on pivot K, with the pivot-column scaling deferred.  Lane (q, c)
 // holds R[4q+v][c] in (ar[v], ai[v]); the matrix of the textbook in-place elimination is
 // A[i][j] = R[i][j] s_j, where s_j = 1 until column j has been the pivot column and
@@ -149,15 +181,23 @@ __device__ __forceinline__ float uniform_read(float v, int lane) {
 //   elsewhere:     R[i][j]  <- R[i][j] - R[i][K] R[K][j] / p
 // Every other update is linear in each column, so a uniform column scale commutes with it.
 // Each lane keeps s_c of its own column c in `scale`.
+// Each lane keeps s_c of its own column c in `scale`.  The pivots of the real layers are
+// also tracked: pmin / pmax hold the bit patterns of the smallest and largest (positive
+// floats order as their bit patterns; a pivot that is not positive fails `ok`).
 template <int K>
 __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& scale, int q,
-                                        int c, int nl, const float (&gd)[16], bool& ok) {
+                                        int c, int nl, const float (&gd)[16], bool& ok,
+                                        unsigned& pmin, unsigned& pmax) {
   constexpr int KV = K & 3;
   constexpr int KQ = K >> 2;
   const float p = uniform_read(ar[KV], 16 * KQ + K);
   // A pivot that is not positive relative to its original diagonal entry means the matrix
   // is not numerically positive definite; padded layers carry an identity block.
-  ok = ok && (K >= nl || p > kPivotRel * gd[K]);
+  ok = ok && (K >= nl || p > PivotRel<float>::v * gd[K]);
+  if (K < nl) {
+    pmin = min(pmin, __float_as_uint(p));
+    pmax = max(pmax, __float_as_uint(p));
+  }
   const float pinv = __builtin_amdgcn_rcpf(p);
   // Row K at this lane's column c (row group K/4, register K%4), scaled; zero in the pivot
   // column so that the rank-1 update leaves that column untouched.
@@ -184,10 +224,11 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& s
 
 template <int K>
 __device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], float& scale, int q,
-                                       int c, int nl, const float (&gd)[16], bool& ok) {
+                                       int c, int nl, const float (&gd)[16], bool& ok,
+                                       unsigned& pmin, unsigned& pmax) {
   if constexpr (K < 16) {
-    gj_step<K>(ar, ai, scale, q, c, nl, gd, ok);
-    gj_all<K + 1>(ar, ai, scale, q, c, nl, gd, ok);
+    gj_step<K>(ar, ai, scale, q, c, nl, gd, ok, pmin, pmax);
+    gj_all<K + 1>(ar, ai, scale, q, c, nl, gd, ok, pmin, pmax);
   }
 }
 
@@ -196,6 +237,164 @@ __device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16])
   if constexpr (K < 16) {
     gd[K] = uniform_read(ar[K & 3], 16 * (K >> 2) + K);
     read_diag<K + 1>(ar, gd);
+  }
+}
+
+__device__ __forceinline__ double pick4(const double (&a)[4], int i) {
+  return i == 0 ? a[0] : i == 1 ? a[1] : i == 2 ? a[2] : a[3];
+}
+
+// The same Gauss-Jordan inversion in FP64, with the pivot index a runtime (wave-uniform)
+// loop variable and every cross-lane move a ds_bpermute or readlane.  Only the NL real
+// pivots are eliminated; the padded identity block is its own inverse.  Leaves G^-1[4q+v][c]
+// in (ar[v], ai[v]).
+template <int NL>
+__device__ __forceinline__ void gj_f64(double (&ar)[4], double (&ai)[4], int q, int c,
+                                       bool& ok) {
+  // Original diagonal entry of this lane's column: G[c][c] is register c % 4 of lane (c/4, c).
+  const double dg = lane_read(pick4(ar, c & 3), 16 * (c >> 2) + c);
+  double scale = 1.0;
+#pragma unroll 1
+  for (int K = 0; K < NL; ++K) {
+    const int KV = K & 3, KQ = K >> 2;
+    const double p = uniform_read(pick4(ar, KV), 16 * KQ + K);
+    ok = ok && p > PivotRel<double>::v * uniform_read(dg, K);
+    const double pinv = 1.0 / p;
+    const bool col_k = (c == K);
+    const double rw = lane_read(pick4(ar, KV), 16 * KQ + c);
+    const double iw = lane_read(pick4(ai, KV), 16 * KQ + c);
+    const double rr = col_k ? 0.0 : rw * pinv;
+    const double ri = col_k ? 0.0 : iw * pinv;
+    scale = col_k ? -pinv : scale;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double cr = lane_read(ar[v], 16 * q + K);  // R[4q+v][K]
+      const double ci = lane_read(ai[v], 16 * q + K);
+      double nr = fma(-cr, rr, fma(ci, ri, ar[v]));
+      double ni = fma(-cr, ri, fma(-ci, rr, ai[v]));
+      if (v == KV && q == KQ) {
+        nr = col_k ? -1.0 : rr;
+        ni = ri;
+      }
+      ar[v] = nr;
+      ai[v] = ni;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    ar[v] *= scale;
+    ai[v] *= scale;
+  }
+}
+
+// The FP64 route for one subcarrier (a wave): Gram, Gauss-Jordan inverse, matched filter,
+// solve and unbiasing in FP64 from the same FP32 channel rows and received samples, giving
+// the outputs of layers 4q .. 4q+3 of data symbol d = c in the lane's xo / vo.  The channel
+// is interpolated in FP64 as (1 - a) v0 + a v1 between the port's two staged pilot rows
+// (a, a multiple of 1/C, is exact in FP32).  Rolled loops and cross-lane reads keep it
+// within the FP32 path's registers: it runs only for the rare subcarriers whose FP32
+// condition estimate exceeds kCondMax (or whose FP32 elimination failed).
+template <int HRES, int NL>
+__device__ __forceinline__ void solve_f64(const Geom& g, const float2* rows, int jlo, int k0,
+                                          int k, int slot, const float2* __restrict__ rx,
+                                          float s2f, int q, int c, float (&xo)[8],
+                                          float (&vo)[4]) {
+  const int NR = g.n_rx, ND = g.n_dsym;
+  const double s2 = s2f;
+  // Layers this lane needs: 4q .. 4q+3 (v = 0..3: rows of G and Z) and c (v = 4: column of
+  // G); padded layers read layer NL-1 and are replaced below.  Row pointers at antenna 0.
+  const float2* b0[5];
+  const float2* b1[5];
+  float wa[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    int l = v < 4 ? 4 * q + v : c;
+    l = l < NL ? l : NL - 1;
+    int r0 = k - k0, r1 = r0;
+    float af = 0.f;
+    if (HRES == 0) {
+      int j0, j1;
+      freq_rule(g, l, k, j0, j1, af);
+      r0 = j0 - jlo;
+      r1 = j1 - jlo;
+    }
+    b0[v] = rows + r0 * NR * NL + l;
+    b1[v] = rows + r1 * NR * NL + l;
+    wa[v] = af;
+  }
+  auto chan = [&](int v, int r, double& re, double& im) {
+    const float2 v0 = b0[v][r * NL];
+    const float2 v1 = b1[v][r * NL];
+    const double w = wa[v];
+    re = (1.0 - w) * (double)v0.x + w * (double)v1.x;
+    im = (1.0 - w) * (double)v0.y + w * (double)v1.y;
+  };
+  // Gram column c, rows 4q .. 4q+3: G[i][c] = sum_r conj(H[r][i]) H[r][c] + s2 delta.
+  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+#pragma unroll 1
+  for (int r = 0; r < NR; ++r) {
+    double cr, ci;
+    chan(4, r, cr, ci);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double hr, hi;
+      chan(v, r, hr, hi);
+      ar[v] = fma(hr, cr, fma(hi, ci, ar[v]));
+      ai[v] = fma(hr, ci, fma(-hi, cr, ai[v]));
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 4 * q + v;
+    const bool in = (i < NL) && (c < NL);
+    ar[v] = in ? ar[v] + ((i == c) ? s2 : 0.0) : ((i == c) ? 1.0 : 0.0);
+    ai[v] = in ? ai[v] : 0.0;
+  }
+  bool ok = true;
+  gj_f64<NL>(ar, ai, q, c, ok);
+  // Matched filter for data symbol d = c (clamped), layers 4q .. 4q+3.
+  const int d = c < ND ? c : ND - 1;
+  const int sym = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
+  const float2* __restrict__ y = rx + ((int64_t)(slot * g.n_symb + sym) * g.n_sc + k) * NR;
+  double zr[4] = {0, 0, 0, 0}, zi[4] = {0, 0, 0, 0};
+#pragma unroll 1
+  for (int r = 0; r < NR; ++r) {
+    const float2 yy = y[r];
+    const double yr = yy.x, yi = yy.y;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double hr, hi;
+      chan(v, r, hr, hi);
+      zr[v] = fma(hr, yr, fma(hi, yi, zr[v]));
+      zi[v] = fma(hr, yi, fma(-hi, yr, zi[v]));
+    }
+  }
+  // X[4q+v][d] = sum_m G^-1[4q+v][m] Z[m][d]: G^-1[4q+v][m] is register v of lane (q, m),
+  // Z[m][d] register m % 4 of lane (m / 4, d).
+  double xr[4] = {0, 0, 0, 0}, xi[4] = {0, 0, 0, 0};
+#pragma unroll 1
+  for (int m = 0; m < NL; ++m) {
+    const int mv = m & 3;
+    const double zmr = mv == 0 ? zr[0] : mv == 1 ? zr[1] : mv == 2 ? zr[2] : zr[3];
+    const double zmi = mv == 0 ? zi[0] : mv == 1 ? zi[1] : mv == 2 ? zi[2] : zi[3];
+    const double br = lane_read(zmr, 16 * (m >> 2) + c);
+    const double bi = lane_read(zmi, 16 * (m >> 2) + c);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double gr = lane_read(ar[v], 16 * q + m);
+      const double gi = lane_read(ai[v], 16 * q + m);
+      xr[v] = fma(gr, br, fma(-gi, bi, xr[v]));
+      xi[v] = fma(gr, bi, fma(gi, br, xi[v]));
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double dl = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
+    const double sd = s2 * dl;
+    const double mu = 1.0 - sd;
+    xo[2 * v] = ok ? (float)(xr[v] / mu) : __builtin_nanf("");
+    xo[2 * v + 1] = ok ? (float)(xi[v] / mu) : __builtin_nanf("");
+    vo[v] = ok ? (float)(sd / mu) : __builtin_inff();
   }
 }
 
@@ -426,86 +625,95 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   read_diag<0>(ar, gd);
   bool ok = true;
   float scale = 1.f;
-  gj_all<0>(ar, ai, scale, q, c, NL, gd, ok);
-  // Apply the deferred column scales: lane (q, c) now holds G^-1[4q+v][c].
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    ar[v] *= scale;
-    ai[v] *= scale;
-  }
-  // Keep the matched filter (the first use of the received samples) after the inversion.
-  __builtin_amdgcn_sched_barrier(0);
-
-  // ---- 5. matched filter Z = H^H Y on the matrix cores ------------------------------------
+  unsigned pmin = 0xFFFFFFFFu, pmax = 0u;
+  gj_all<0>(ar, ai, scale, q, c, NL, gd, ok, pmin, pmax);
+  // Subcarriers whose system is too ill-conditioned for FP32 (or not numerically positive
+  // definite in FP32) are solved again in FP64 once the FP32 solution is done (the decision
+  // is uniform over the wave; placed after the FP32 route, the FP64 route's registers do not
+  // compete with it).
+  const bool f64 = !ok || __uint_as_float(pmax) > kCondMax * __uint_as_float(pmin);
+  float xo[8], vo[4];
   {
-    float yr[16], yi[16];
+    // Apply the deferred column scales: lane (q, c) now holds G^-1[4q+v][c].
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      yr[2 * i] = yv[i].x;
-      yi[2 * i] = yv[i].y;
-      yr[2 * i + 1] = yv[i].z;
-      yi[2 * i + 1] = yv[i].w;
+    for (int v = 0; v < 4; ++v) {
+      ar[v] *= scale;
+      ai[v] *= scale;
     }
-    if constexpr (PREC == kPrecF32) {
-      // Three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
-      //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
-      floatx4 acc_m1 = acc_g, acc_m2 = acc_g, acc_m3 = acc_g;
+    // Keep the matched filter (the first use of the received samples) after the inversion.
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- 5. matched filter Z = H^H Y on the matrix cores ----------------------------------
+    {
+      float yr[16], yi[16];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc_m1[v] = acc_m2[v] = acc_m3[v] = 0.f;
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        acc_m1 = mfma(hr[s], yr[s], acc_m1);
-        acc_m2 = mfma(hi[s], yi[s], acc_m2);
-        acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
+      for (int i = 0; i < 8; ++i) {
+        yr[2 * i] = yv[i].x;
+        yi[2 * i] = yv[i].y;
+        yr[2 * i + 1] = yv[i].z;
+        yi[2 * i + 1] = yv[i].w;
       }
+      if constexpr (PREC == kPrecF32) {
+        // Three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
+        //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
+        floatx4 acc_m1 = acc_g, acc_m2 = acc_g, acc_m3 = acc_g;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        z_r[v] = acc_m1[v] + acc_m2[v];
-        z_i[v] = acc_m3[v] - acc_m1[v] + acc_m2[v];
+        for (int v = 0; v < 4; ++v) acc_m1[v] = acc_m2[v] = acc_m3[v] = 0.f;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          acc_m1 = mfma(hr[s], yr[s], acc_m1);
+          acc_m2 = mfma(hi[s], yi[s], acc_m2);
+          acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          z_r[v] = acc_m1[v] + acc_m2[v];
+          z_i[v] = acc_m3[v] - acc_m1[v] + acc_m2[v];
+        }
+      } else if constexpr (PREC == kPrecF16) {
+        mf_lowp<half8, _Float16>(h16, yr, yi, z_r, z_i);
+      } else {
+        mf_lowp<bf16x8, __bf16>(hb16, yr, yi, z_r, z_i);
       }
-    } else if constexpr (PREC == kPrecF16) {
-      mf_lowp<half8, _Float16>(h16, yr, yi, z_r, z_i);
-    } else {
-      mf_lowp<bf16x8, __bf16>(hb16, yr, yi, z_r, z_i);
+    }
+
+    // ---- 6. X_hat = G^-1 Z on the matrix cores -------------------------------------------
+    // A[i = c][m = 4q + s] = G^-1[c][4q+s] = conj(G^-1[4q+s][c]) = (ar[s], -ai[s]);
+    // B[m = 4q + s][d = c] = Z[4q+s][c].
+    // Three real products again: Re = ar zr + ai zi,  Im = (ar - ai)(zr + zi) - ar zr + ai zi.
+    floatx4 acc_n1 = {0.f, 0.f, 0.f, 0.f}, acc_n2 = acc_n1, acc_n3 = acc_n1;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float zr = z_r[s];
+      const float zi = z_i[s];
+      acc_n1 = mfma(ar[s], zr, acc_n1);
+      acc_n2 = mfma(ai[s], zi, acc_n2);
+      acc_n3 = mfma(ar[s] - ai[s], zr + zi, acc_n3);
+    }
+    floatx4 acc_xr, acc_xi;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc_xr[v] = acc_n1[v] + acc_n2[v];
+      acc_xi[v] = acc_n3[v] - acc_n1[v] + acc_n2[v];
+    }
+
+    // ---- 7. unbias: lane (q, d = c) holds layers 4q .. 4q+3 of data symbol d ------------
+    float dl[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float sd = s2 * dl[v];
+      const float im = __builtin_amdgcn_rcpf(1.f - sd);
+      xo[2 * v] = acc_xr[v] * im;
+      xo[2 * v + 1] = acc_xi[v] * im;
+      vo[v] = sd * im;
     }
   }
-
-  // ---- 6. X_hat = G^-1 Z on the matrix cores ---------------------------------------------
-  // A[i = c][m = 4q + s] = G^-1[c][4q+s] = conj(G^-1[4q+s][c]) = (ar[s], -ai[s]);
-  // B[m = 4q + s][d = c] = Z[4q+s][c].
-  // Three real products again: Re = ar zr + ai zi,  Im = (ar - ai)(zr + zi) - ar zr + ai zi.
-  floatx4 acc_n1 = {0.f, 0.f, 0.f, 0.f}, acc_n2 = acc_n1, acc_n3 = acc_n1;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const float zr = z_r[s];
-    const float zi = z_i[s];
-    acc_n1 = mfma(ar[s], zr, acc_n1);
-    acc_n2 = mfma(ai[s], zi, acc_n2);
-    acc_n3 = mfma(ar[s] - ai[s], zr + zi, acc_n3);
-  }
-  floatx4 acc_xr, acc_xi;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    acc_xr[v] = acc_n1[v] + acc_n2[v];
-    acc_xi[v] = acc_n3[v] - acc_n1[v] + acc_n2[v];
-  }
-
-  // ---- 7. unbias and store: lane (q, d = c) holds layers 4q .. 4q+3 of data symbol d ------
-  float dl[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
+  if (f64) solve_f64<HRES, NL>(g, lds_h, jlo, k0, k, slot, rx, s2, q, c, xo, vo);
   const int d = c;
   const bool mine = live && d < ND && 4 * q < NL;
   const int64_t o = ((int64_t)(slot * ND + (d < ND ? d : 0)) * g.n_sc + k) * NL;
-  float xo[8], vo[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const float sd = s2 * dl[v];
-    const float im = __builtin_amdgcn_rcpf(1.f - sd);
-    xo[2 * v] = ok ? acc_xr[v] * im : __builtin_nanf("");
-    xo[2 * v + 1] = ok ? acc_xi[v] * im : __builtin_nanf("");
-    vo[v] = ok ? sd * im : __builtin_inff();
-  }
   // Layers 4q .. 4q+3 of one RE: 32 contiguous bytes of x, 16 of nv.
   if (mine && x != nullptr) {
     if (NL % 4 == 0) {

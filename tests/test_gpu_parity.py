@@ -355,6 +355,67 @@ def test_reduced_precision_sinr_loss_64x16():
         say("; ".join(line))
 
 
+def ill_conditioned_case():
+    """Two slots at a matrix-core shape (16 Rx x 8 layers, full-resolution channel given):
+    slot 0 (s2 = 1e-6) holds i.i.d. subcarriers, near-collinear layers 1/2 (delta 1e-6) and
+    exactly collinear layers 1/2 (regularised by s2 alone); slot 1 (s2 = 0, zero forcing)
+    holds i.i.d. subcarriers, identical layers 4/5 (singular) and near-collinear layers 4/5
+    (delta 1e-4, kappa ~ 1e9)."""
+    shape = SlotShape(2, 14, 16, 8, 4, 4, 2, (2,), 2)
+    nsc, NR, NL, ND = shape.n_sc, shape.n_rx, shape.n_layers, shape.n_dsym
+    rng = np.random.default_rng(21)
+    cn = lambda *sz: ((rng.standard_normal(sz) + 1j * rng.standard_normal(sz)) / np.sqrt(2))
+    H = cn(2, nsc, NR, NL).astype(np.complex64)
+    w = cn(nsc, NR).astype(np.complex64)
+    H[0, 8:16, :, 2] = H[0, 8:16, :, 1] + np.complex64(1e-6) * w[8:16]
+    H[0, 16:, :, 2] = H[0, 16:, :, 1]
+    H[1, 8:16, :, 5] = H[1, 8:16, :, 4]
+    H[1, 16:, :, 5] = H[1, 16:, :, 4] + np.complex64(1e-4) * w[16:]
+    bits = rng.integers(0, 2, (2, ND, nsc, NL, shape.qm)).astype(np.uint8)
+    x = synth.qam_map(bits, shape.qm)
+    nvar = np.array([1e-6, 0.0], np.float32)
+    rx = np.zeros((2, shape.n_symb, nsc, NR), np.complex64)
+    for di, s in enumerate(shape.data_symbols()):
+        rx[:, s] = np.einsum("bkrl,bkl->bkr", H.astype(np.complex128), x[:, di])
+    rx[0] += (1e-3 * cn(shape.n_symb, nsc, NR)).astype(np.complex64)
+    Gc = np.einsum("bkrl,bkrm->bklm", H.conj().astype(np.complex128), H.astype(np.complex128))
+    Gc = Gc + nvar[:, None, None, None] * np.eye(NL)
+    kappa = np.linalg.cond(Gc)  # [slot][sc]
+    return shape, H[:, None], rx, nvar, kappa
+
+
+@pytest.mark.parametrize("prec", [ranphy.PREC_FP32, ranphy.PREC_FP16, ranphy.PREC_BF16])
+def test_fp64_route_for_ill_conditioned_grams(prec):
+    # Subcarriers whose Gram condition estimate exceeds 1e6 (or whose FP32 elimination
+    # fails) are solved in FP64 from the FP32 channel and samples.  Where kappa > 1e6 an FP32
+    # solve is off by O(1) (forward-error bound 8 kappa Nl 2^-24 >> 1), so agreement with the
+    # FP64 oracle to 1e-4 shows the FP64 route ran; exactly singular systems (zero forcing
+    # with identical layers) give NaN / +inf on both sides.
+    shape, h, rx, nvar, kappa = ill_conditioned_case()
+    say(f"ill-conditioned Grams prec={prec}: kappa per subcarrier "
+        f"{np.array2string(np.log10(kappa), precision=1, max_line_width=200)}")
+    x, nv = ranphy.mmse_detect(shape, dev(rx), dev(h), dev(nvar), h_res=ranphy.H_FULL,
+                               precision=prec)
+    xg, nvg = host(x, out_shape(shape)), host(nv, out_shape(shape))
+    xr, nvr = oracle.mmse_detect(shape, rx, h, ranphy.H_FULL, nvar)
+    singular = np.zeros(kappa.shape, bool)
+    singular[1, 8:16] = True
+    assert np.all(np.isnan(xr[1][:, 8:16])) and np.all(np.isinf(nvr[1][:, 8:16]))
+    assert np.all(np.isnan(xg[1][:, 8:16])) and np.all(np.isinf(nvg[1][:, 8:16]))
+    ill = (kappa > 1e6) & ~singular
+    assert ill.sum() == 24  # slot 0 sc 8..23, slot 1 sc 16..23
+    with np.errstate(invalid="ignore"):  # the singular REs (inf - inf), excluded below
+        err_x = np.linalg.norm(xg - xr, axis=-1) / np.linalg.norm(xr, axis=-1)  # [slot][d][sc]
+        err_v = np.max(np.abs(nvg - nvr) / np.maximum(np.abs(nvr), 1e-30), axis=-1)
+    sel = np.broadcast_to(ill[:, None, :], err_x.shape)
+    say(f"  kappa > 1e6: {int(sel.sum())} REs, max rel err x {err_x[sel].max():.2e} "
+        f"nv {err_v[sel].max():.2e}")
+    assert err_x[sel].max() <= 1e-4 and err_v[sel].max() <= 1e-4
+    if prec == ranphy.PREC_FP32:
+        well = np.broadcast_to((kappa < 1e4)[:, None, :], err_x.shape)
+        assert err_x[well].max() <= 1e-4, err_x[well].max()
+
+
 FUSED = ["m", "prb5_l9_r32", "prb3_l12_r48", "prb2_l5_r16", "prb4_l8_short",
          "prb1_l16_dmrs_end"]
 
