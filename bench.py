@@ -151,12 +151,70 @@ def detection_quality(torch, ranphy, synth):
     return out
 
 
+def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, fused, scs_hz, reps=200):
+    """One slot through the whole chain: mean time per slot launched eagerly (one call per
+    step, synchronised at the end) and replayed from a HIP graph holding the slot's launches;
+    the replayed LLRs must equal the eager ones bit for bit."""
+    one = shape.with_slots(1)
+    dev = rx.device
+    n_rx = ranphy.buffer_floats(one, ranphy.BUF_RX) // 2
+    n_pil = ranphy.buffer_floats(one, ranphy.BUF_PILOTS) // 2
+    rx1, pil1, nv1 = rx[:n_rx], pil[:n_pil], nvar[:1]
+    h1 = torch.empty(ranphy.buffer_floats(one, ranphy.BUF_H, h_res) // 2, dtype=torch.complex64, device=dev)
+    x1 = torch.empty(ranphy.buffer_floats(one, ranphy.BUF_X) // 2, dtype=torch.complex64, device=dev)
+    v1 = torch.empty(ranphy.buffer_floats(one, ranphy.BUF_NV), dtype=torch.float32, device=dev)
+    l1 = torch.empty(ranphy.buffer_floats(one, ranphy.BUF_LLR), dtype=torch.float32, device=dev)
+
+    def chain():
+        ranphy.chest_ls(one, rx1, pil1, h=h1, h_res=h_res)
+        if fused:
+            ranphy.mmse_llr(one, rx1, h1, nv1, h_res=h_res, llr=l1, precision=prec)
+        else:
+            ranphy.mmse_detect(one, rx1, h1, nv1, h_res=h_res, x=x1, nv=v1, precision=prec)
+            ranphy.llr_demap(one, x1, v1, llr=l1)
+
+    def timed(fn):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e3
+
+    eager_us = timed(chain)
+    ref = l1.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capturing stream
+        chain()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        chain()
+    graph_us = timed(graph.replay)
+    l1.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(l1.view(torch.int32), ref.view(torch.int32)))
+    slot_us = 1000.0 * 15e3 / scs_hz  # 14-symbol slot: 1 ms at 15 kHz, 0.5 ms at 30 kHz
+    return {"eager_us": round(eager_us, 2), "graph_us": round(graph_us, 2),
+            "graph_matches_eager": same, "slot_duration_us": slot_us,
+            "data_re_per_slot": one.n_dsym * one.n_sc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="m", choices=["m", "c2", "c1"])
+    ap.add_argument("--workload", default="m", choices=["m", "c2", "c1", "p2", "p4", "p8"],
+                    help="m: 64x16 (default); c1/c2: 4x2 and 16x4; p2/p4/p8: the paper's "
+                         "square 2x2/4x4/8x8 at 60 RB, 15 kHz")
     ap.add_argument("--slots", type=int, default=None, help="override the batch size")
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
@@ -165,6 +223,9 @@ def main():
                     help="fused detection + demapping (matrix-core shapes) or three calls")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the one-slot latency runs (profiled runs: they launch the same "
+                         "kernels at one-slot size)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16/BF16 detector runs and the SINR comparison")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
@@ -299,6 +360,9 @@ def main():
             "GB/s": cc["bytes"] / (kern_ms[n] * 1e-3) / 1e9,
             "TFLOP/s": cc["flops"] / (kern_ms[n] * 1e-3) / 1e12,
             "bytes_per_launch": cc["bytes"], "flops_per_launch": cc["flops"]}
+    if not args.no_latency:
+        out["slot_latency"] = slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec,
+                                           fused, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])
     if args.workload == "m" and h_res == ranphy.H_PILOT and not args.no_variants:
         variants = {}
         quality = detection_quality(torch, ranphy, synth)

@@ -352,8 +352,12 @@ __device__ __forceinline__ void solve_f64(const Geom& g, const float2* rows, int
   }
   bool ok = true;
   gj_f64<NL>(ar, ai, q, c, ok);
-  // Matched filter for data symbol d = c (clamped), layers 4q .. 4q+3.
-  const int d = c < ND ? c : ND - 1;
+  // Matched filter for data symbol d = c (clamped), layers 4q .. 4q+3.  The lane index is
+  // passed through an empty asm so that the sample address is recomputed here rather than
+  // shared with (and kept alive from) the FP32 route's loads of the same row.
+  int cl = c;
+  asm volatile("" : "+v"(cl));
+  const int d = cl < ND ? cl : ND - 1;
   const int sym = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
   const float2* __restrict__ y = rx + ((int64_t)(slot * g.n_symb + sym) * g.n_sc + k) * NR;
   double zr[4] = {0, 0, 0, 0}, zi[4] = {0, 0, 0, 0};

@@ -120,6 +120,19 @@ CONFIGS: Dict[str, dict] = {
         snr_db=(0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0), slots_per_snr=20),
 }
 
+# The paper's own evaluation shapes (Sec. V): square 2x2, 4x4 and 8x8 MIMO over 60 RB at
+# 15 kHz, MCS 9 (QPSK), 14-symbol slots.  DMRS: comb C and time cover T with C T >= layers
+# (2x2: comb 2 on symbol 2; 4x4: comb 2, double symbol; 8x8: comb 4, double symbol).  The
+# paper's TDL-C table is not available; an exponential PDP with 300 ns rms delay spread
+# stands in for it, as for the other workloads.
+for _n, (_cid, _nl, _c, _t) in {"p2": (4, 2, 2, 1), "p4": (5, 4, 2, 2), "p8": (6, 8, 4, 2)}.items():
+    CONFIGS[_n] = dict(
+        config_id=_cid,
+        shape=SlotShape(n_prb=60, n_symb=14, n_rx=_nl, n_layers=_nl, qm=2, dmrs_comb=_c,
+                        dmrs_td=_t, dmrs_sym0=(2,), n_slots=1),
+        scs_hz=15e3, pdp=("exp", 300e-9),
+        snr_db=(0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0), slots_per_snr=100)
+
 
 def rng_for(config_id: int, snr_index: int, slot: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(

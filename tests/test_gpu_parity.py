@@ -156,6 +156,10 @@ SHAPES = {
     "prb2_l5_r16": SlotShape(2, 14, 16, 5, 2, 4, 2, (2,), 3),
     "prb4_l8_short": SlotShape(4, 7, 16, 8, 4, 4, 2, (0,), 2),
     "prb1_l16_dmrs_end": SlotShape(1, 14, 64, 16, 8, 8, 2, (12,), 2),
+    # the paper's square shapes at 60 RB
+    "p2": synth.CONFIGS["p2"]["shape"].with_slots(2),
+    "p4": synth.CONFIGS["p4"]["shape"].with_slots(2),
+    "p8": synth.CONFIGS["p8"]["shape"].with_slots(2),
 }
 
 
@@ -484,6 +488,53 @@ def test_fused_detect_demap_empty_batch():
     ef = torch.empty(0, dtype=torch.float32, device="cuda")
     ranphy.mmse_llr(shape, e, e, ef, llr=ef)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["p2", "p4", "p8"])
+def test_end_to_end_paper_shapes(name):
+    # Square 2x2 / 4x4 / 8x8 at 60 RB, 15 kHz, QPSK: GPU chain vs FP64 oracle chain.
+    b = synth.make_batch(name, n_slots=7, snr_db=synth.CONFIGS[name]["snr_db"])
+    shape = b["shape"]
+    say(f"end to end {name}: {shape.n_rx}x{shape.n_layers}")
+    xg, lg, xr, nvr, lr = end_to_end(shape, b["rx"], b["pilots"], b["noise_var"])
+    ok = check_end_to_end(shape, xg, lg, xr, lr)
+    assert (~ok).mean() < 1e-3
+
+
+def test_graph_replay_matches_eager():
+    # One slot's chest_ls -> mmse_llr captured in a HIP graph: every replay, with eager work
+    # and synchronisations in between, equals the eager result bit for bit.
+    shape = SHAPES["prb5_l9_r32"].with_slots(1)
+    rx, pil, nvar, *_ = make_inputs(shape, 12)
+    rxd, pd, nd = dev(rx), dev(pil), dev(nvar)
+    h = torch.empty(ranphy.buffer_floats(shape, ranphy.BUF_H) // 2, dtype=torch.complex64,
+                    device="cuda")
+    llr = torch.empty(ranphy.buffer_floats(shape, ranphy.BUF_LLR), dtype=torch.float32,
+                      device="cuda")
+
+    def chain():
+        ranphy.chest_ls(shape, rxd, pd, h=h)
+        ranphy.mmse_llr(shape, rxd, h, nd, llr=llr)
+
+    chain()
+    torch.cuda.synchronize()
+    ref = llr.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        chain()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        chain()
+    for i in range(4):
+        llr.fill_(float(i))       # eager work between replays
+        h.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(llr.view(torch.int32), ref.view(torch.int32)), i
 
 
 def test_llr_demap_8_byte_aligned_buffers():
