@@ -22,7 +22,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fvisibility=hidden", "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC]
+         "-fvisibility=hidden", "-Wno-unused-command-line-argument",
+         # the matrix-core detector asks for 5 waves per SIMD; its full-resolution 14..16
+         # layer instances are held to 4 by their LDS, which the compiler reports as a warning
+         "-Wno-pass-failed",
+         "-I", INCLUDE, "-I", CSRC]
 
 
 def sources():

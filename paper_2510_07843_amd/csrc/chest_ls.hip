@@ -1,6 +1,6 @@
 // DMRS least-squares channel estimation (channel estimation is one of the PHY blocks the
 // paper's Sec. III-B names as suited to data-level parallelism; LS is the standard
-// estimator).  One thread per output value; the value is
+// estimator).  The value of each output is
 //   h(o, j, r, p) = (1/T) sum_t rx(sym0[o] + t, k, r) conj(pilot(o, t, j, p)),
 //   k = (p mod C) + C j,
 // and for the full-resolution output the linear interpolation between the port's two
@@ -81,6 +81,72 @@ __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* 
   }
 }
 
+// Pilot resolution for small arrays: one block per (slot, occasion, run of up to jb
+// consecutive pilot indices), so that every block has work for its 256 threads.  Pilots j0 .. j0 + jb - 1 of every comb offset sit on the C jb contiguous
+// subcarriers C j0 .. C (j0 + jb) - 1, so the run's samples on each of the T DMRS symbols are
+// C jb Nr contiguous values: read with consecutive threads on consecutive values into LDS,
+// rows padded by one value so that threads of different comb offsets read different banks.
+// The run's output rows h[j][rx][layer] (jb Nr Nl contiguous values) are written
+// contiguously.  jb = 1 takes chest_pilot_kernel, which needs fewer index divisions.
+constexpr int kRunPadded = 520;  // C jb (Nr + 1) <= 520 values per DMRS symbol
+constexpr int kRunPilots = 512;  // T jb Nl <= 512 pilot values
+
+template <int T>
+__global__ void __launch_bounds__(256) chest_run_kernel(Geom g, const float2* __restrict__ rx,
+                                                          const float2* __restrict__ pil,
+                                                          float2* __restrict__ h, int jb) {
+  __shared__ float2 ys[T * kRunPadded];
+  __shared__ float2 ps[kRunPilots];
+  const int C = g.comb, NR = g.n_rx, NL = g.n_layers;
+  const int nrun = (g.n_pilot + jb - 1) / jb;
+  const int run = blockIdx.x % nrun;
+  const int so = blockIdx.x / nrun;  // slot * n_occ + occasion
+  const int o = so % g.n_occ;
+  const int64_t slot = so / g.n_occ;
+  const int j0 = run * jb;
+  const int nj = min(jb, g.n_pilot - j0);
+  const int pitch = NR + 1;
+  const int rowv = C * nj * NR;  // the run's values per DMRS symbol
+  for (int f = threadIdx.x; f < T * rowv; f += 256) {
+    const int t = f / rowv;
+    const int rem = f - t * rowv;
+    const int kk = rem / NR;  // subcarrier offset in the run
+    const int r = rem - kk * NR;
+    const int k = C * j0 + kk;
+    float2 v = make_float2(0.f, 0.f);
+    if (k < g.n_sc) v = rx[((slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k) * NR + r];
+    ys[(t * C * jb + kk) * pitch + r] = v;
+  }
+  for (int f = threadIdx.x; f < T * nj * NL; f += 256) {
+    const int t = f / (nj * NL);
+    const int rem = f - t * (nj * NL);
+    const int jj = rem / NL;
+    const int p = rem - jj * NL;
+    ps[(t * jb + jj) * NL + p] = pil[(((int64_t)so * T + t) * g.n_pilot + j0 + jj) * NL + p];
+  }
+  __syncthreads();
+  float2* __restrict__ dst = h + ((int64_t)so * g.n_pilot + j0) * NR * NL;
+  const float inv = 1.f / (float)T;
+  for (int e = threadIdx.x; e < nj * NR * NL; e += 256) {
+    const int jj = e / (NR * NL);
+    const int rem = e - jj * (NR * NL);
+    const int r = rem / NL;
+    const int p = rem - r * NL;
+    const int c = p & (C - 1);
+    const int kk = C * jj + c;
+    float2 acc = make_float2(0.f, 0.f);
+    if (C * j0 + kk < g.n_sc) {
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const float2 m = cmulc(ps[(t * jb + jj) * NL + p], ys[(t * C * jb + kk) * pitch + r]);
+        acc.x += m.x;  // y conj(q)
+        acc.y += m.y;
+      }
+    }
+    dst[e] = make_float2(acc.x * inv, acc.y * inv);
+  }
+}
+
 template <int T>
 __global__ void __launch_bounds__(256) chest_full_kernel(Geom g, const float2* __restrict__ rx,
                                                          const float2* __restrict__ pil,
@@ -113,9 +179,18 @@ hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots
   if (total == 0) return hipSuccess;
   const dim3 block(256), grid((unsigned)((total + 255) / 256));
   if (h_res == 0) {
-    const dim3 pgrid((unsigned)((int64_t)g.n_slots * g.n_occ * g.n_pilot));
-    if (g.td == 1) hipLaunchKernelGGL(chest_pilot_kernel<1>, pgrid, block, 0, s, g, rx, pilots, h);
-    else hipLaunchKernelGGL(chest_pilot_kernel<2>, pgrid, block, 0, s, g, rx, pilots, h);
+    int jb = min(kRunPadded / (g.comb * (g.n_rx + 1)), kRunPilots / (g.td * g.n_layers));
+    jb = max(1, min(64, jb));
+    const int nrun = (g.n_pilot + jb - 1) / jb;
+    const dim3 pgrid((unsigned)((int64_t)g.n_slots * g.n_occ * nrun));
+    if (jb == 1) {
+      if (g.td == 1) hipLaunchKernelGGL(chest_pilot_kernel<1>, pgrid, block, 0, s, g, rx, pilots, h);
+      else hipLaunchKernelGGL(chest_pilot_kernel<2>, pgrid, block, 0, s, g, rx, pilots, h);
+    } else if (g.td == 1) {
+      hipLaunchKernelGGL(chest_run_kernel<1>, pgrid, block, 0, s, g, rx, pilots, h, jb);
+    } else {
+      hipLaunchKernelGGL(chest_run_kernel<2>, pgrid, block, 0, s, g, rx, pilots, h, jb);
+    }
   } else {
     if (g.td == 1) hipLaunchKernelGGL(chest_full_kernel<1>, grid, block, 0, s, g, rx, pilots, h);
     else hipLaunchKernelGGL(chest_full_kernel<2>, grid, block, 0, s, g, rx, pilots, h);

@@ -71,6 +71,10 @@ hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots
                            int h_res, hipStream_t s);
 hipError_t launch_mmse_re(const Geom& g, const float2* rx, const float2* h, int h_res,
                           const float* noise_var, float2* x, float* nv, hipStream_t s);
+// One thread per subcarrier (one DMRS occasion, Nr in {1,2,4,8}, Nl <= 8, Nr Nl <= 64).
+bool mmse_sc_eligible(const Geom& g);
+hipError_t launch_mmse_sc(const Geom& g, const float2* rx, const float2* h, int h_res,
+                          const float* nvar, float2* x, float* nv, hipStream_t s);
 hipError_t launch_llr_demap(const Geom& g, const float2* x, const float* nv, float* llr,
                             hipStream_t s);
 

@@ -165,6 +165,13 @@ int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx, const fl
   if (mfma)
     return ranphy::status_of(
         ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, nullptr, precision, s));
+  // Small arrays with one DMRS occasion: one thread per subcarrier shares the Gram and its
+  // factorisation over the data symbols, once the batch has a subcarrier for every lane of
+  // the chip (256 CUs x 4 SIMDs x 64 lanes); smaller batches (a single slot) finish sooner
+  // with one thread per resource element.
+  constexpr int64_t kScMinThreads = 256 * 4 * 64;
+  if (ranphy::mmse_sc_eligible(g) && (int64_t)g.n_slots * g.n_sc >= kScMinThreads)
+    return ranphy::status_of(ranphy::launch_mmse_sc(g, rx2, h2, h_res, noise_var, x2, nv, s));
   return ranphy::status_of(ranphy::launch_mmse_re(g, rx2, h2, h_res, noise_var, x2, nv, s));
 }
 

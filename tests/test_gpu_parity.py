@@ -490,6 +490,30 @@ def test_fused_detect_demap_empty_batch():
     torch.cuda.synchronize()
 
 
+SMALL_BATCHED = {
+    # >= 65536 subcarriers per call: the one-thread-per-subcarrier detector
+    "p2": synth.CONFIGS["p2"]["shape"].with_slots(92),
+    "p4": synth.CONFIGS["p4"]["shape"].with_slots(92),
+    "p8": synth.CONFIGS["p8"]["shape"].with_slots(92),
+    "r8_l3_c8": SlotShape(60, 14, 8, 3, 4, 8, 1, (3,), 92),
+    "r4_l1_short": SlotShape(60, 7, 4, 1, 2, 2, 1, (0,), 184),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL_BATCHED))
+@pytest.mark.parametrize("h_res", [ranphy.H_PILOT, ranphy.H_FULL])
+def test_mmse_small_mimo_batched(name, h_res):
+    shape = SMALL_BATCHED[name]
+    say(f"mmse_detect batched {name} h_res={h_res}: {shape.n_slots * shape.n_sc} subcarriers")
+    assert shape.n_slots * shape.n_sc >= 65536
+    rx, pil, nvar, *_ = make_inputs(shape, 3, snr_db=12.0)
+    nvar = nvar * np.linspace(0.5, 2.0, shape.n_slots).astype(np.float32)
+    h = oracle.chest_ls(shape, rx, pil, h_res).astype(np.complex64)
+    xg, nvg = gpu_mmse(shape, rx, h, h_res, nvar)
+    xr, nvr = oracle.mmse_detect(shape, rx, h, h_res, nvar)
+    check_mmse(shape, h, h_res, nvar, xg, nvg, xr, nvr)
+
+
 @pytest.mark.parametrize("name", ["p2", "p4", "p8"])
 def test_end_to_end_paper_shapes(name):
     # Square 2x2 / 4x4 / 8x8 at 60 RB, 15 kHz, QPSK: GPU chain vs FP64 oracle chain.
