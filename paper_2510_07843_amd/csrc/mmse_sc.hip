@@ -1,5 +1,5 @@
 // Linear MMSE detection for small MIMO shapes with one DMRS occasion: Nr in {1, 2, 4, 8},
-// Nl <= 8, Nr Nl <= 64 (the paper's square 2x2 / 4x4 / 8x8 evaluation shapes, Sec. V).
+// Nl <= 8, Nr Nl <= 64 (the paper's square 2x2 / 4x4 / 8x8 evaluation shapes, Sec. IV).
 //
 // With one occasion the channel estimate is held over the slot (no time interpolation), so
 // the Gram G = H^H H + s2 I, its factorisation, d_l = (G^-1)_ll and the MMSE filter

@@ -120,7 +120,7 @@ CONFIGS: Dict[str, dict] = {
         snr_db=(0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0), slots_per_snr=20),
 }
 
-# The paper's own evaluation shapes (Sec. V): square 2x2, 4x4 and 8x8 MIMO over 60 RB at
+# The paper's own evaluation shapes (Sec. IV): square 2x2, 4x4 and 8x8 MIMO over 60 RB at
 # 15 kHz, MCS 9 (QPSK), 14-symbol slots.  DMRS: comb C and time cover T with C T >= layers
 # (2x2: comb 2 on symbol 2; 4x4: comb 2, double symbol; 8x8: comb 4, double symbol).  The
 # paper's TDL-C table is not available; an exponential PDP with 300 ns rms delay spread
