@@ -181,6 +181,62 @@ RANPHY_API int ranphy_mmse_llr(const ranphy_slot_desc* d, const float* rx, const
 RANPHY_API int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const float* nv, float* llr,
                      void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned refinement of the pilot-resolution channel estimate (a library addition beside
+ * the paper's method: channel estimation is the PHY block the paper names besides MIMO
+ * detection, abstract and Sec. III-B).
+ *
+ * Network: 4 layers of 3x3 correlation with zero padding over an image grid of `rows` x `cols`
+ * pixels, channels 2 -> 32 -> 32 -> 32 -> 2, ReLU after the first three, last layer y.  Tap
+ * t = 3 (dy + 1) + (dx + 1) reads pixel (row + dy, col + dx).  BF16 operands, FP32
+ * accumulation.
+ * Noise normalisation: with a noise variance s2_g > 0 per group (noise_var, device, may be
+ * NULL: s2 = 1 for every group) the network sees x / sigma_g, sigma_g = sqrt(s2_g), and the
+ * refined tensor is x + sigma_g y; training measures (x / sigma_g + y - target / sigma_g)^2,
+ * summed and divided by the number of values, so that every SNR weighs alike.
+ *
+ * Parameters: one FP32 vector of ranphy_cnn_param_count() floats, per layer l = 0..3:
+ * W_l[9][32 in][32 out] then b_l[32]; channels beyond a layer's real ones (2 inputs of layer
+ * 0, 2 outputs of layer 3) must be zero and stay zero.
+ * Tensors: x, target, out [group][pixel = row * cols + col][image][2] FP32 (real, imaginary).
+ * A pilot-resolution estimate h[slot][occ][j][rx][layer] is such a tensor with
+ * group = slot, rows = occasions, cols = pilots, image = rx * n_layers + layer.
+ * Workspace: device memory of ranphy_cnn_workspace_bytes(..) bytes, 256-byte aligned,
+ * owned by the caller; its contents need not be initialised.  Errors as above.
+ * ------------------------------------------------------------------------------------- */
+RANPHY_API int64_t ranphy_cnn_param_count(void);
+/* Workspace bytes for a forward pass (train = 0) or a gradient pass (train = 1). */
+RANPHY_API int64_t ranphy_cnn_workspace_bytes(int rows, int cols, int n_img, int n_groups,
+                                              int train);
+/* out = x + sigma y (x + y without noise variances); groups whose noise variance is below
+ * min_noise_var, or not positive, keep out = x.  out may alias x. */
+RANPHY_API int ranphy_cnn_forward(const float* params, const float* x, const float* noise_var,
+                                  float min_noise_var, float* out, int rows, int cols,
+                                  int n_img, int n_groups, void* workspace,
+                                  int64_t workspace_bytes, void* stream);
+/* loss (one float, device) and its gradient with respect to every parameter (grad: same
+ * layout as params; zero on the padded channels).  Every group's noise variance must be
+ * positive. */
+RANPHY_API int ranphy_cnn_grad(const float* params, const float* x, const float* target,
+                               const float* noise_var, float* grad, float* loss, int rows,
+                               int cols, int n_img, int n_groups, void* workspace,
+                               int64_t workspace_bytes, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) of step number `step` >= 1 on params with
+ * first and second moments m, v (zero before step 1). */
+RANPHY_API int ranphy_cnn_adam(float* params, const float* grad, float* m, float* v, int step,
+                               float lr, void* stream);
+/* The network applied to a pilot-resolution estimate (ranphy_chest_ls with RANPHY_H_PILOT),
+ * h_out in the same layout (may alias h_in).  Slots whose noise variance noise_var[slot]
+ * (device, as for ranphy_mmse_detect; may be NULL: every slot refined) is below
+ * min_noise_var keep the plain estimate: above the SNR where validation shows the refinement
+ * no longer helps, plain interpolation of the LS estimate is the better one.  Processed in as
+ * many slots per pass as the workspace holds (at least ranphy_cnn_workspace_bytes(n_occ,
+ * ceil(n_sc / C), n_rx * n_layers, 1, 0) bytes). */
+RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params,
+                                  const float* noise_var, float min_noise_var,
+                                  const float* h_in, float* h_out, void* workspace,
+                                  int64_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

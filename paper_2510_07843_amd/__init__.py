@@ -33,7 +33,8 @@ BUF_RX, BUF_PILOTS, BUF_H, BUF_NOISE_VAR, BUF_X, BUF_NV, BUF_LLR = range(7)
 EXPORTED_SYMBOLS = (
     "ranphy_abi_version", "ranphy_status_str", "ranphy_buffer_floats",
     "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_mmse_llr",
-    "ranphy_llr_demap",
+    "ranphy_llr_demap", "ranphy_cnn_param_count", "ranphy_cnn_workspace_bytes",
+    "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
 )
 
 
@@ -90,8 +91,17 @@ def lib() -> ctypes.CDLL:
         L.ranphy_mmse_detect_prec.argtypes = [D, P, P, ctypes.c_int, P, P, P, ctypes.c_int, P]
         L.ranphy_mmse_llr.argtypes = [D, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
         L.ranphy_llr_demap.argtypes = [D, P, P, P, P]
+        I, I64 = ctypes.c_int, ctypes.c_int64
+        L.ranphy_cnn_param_count.restype = I64
+        L.ranphy_cnn_workspace_bytes.argtypes = [I, I, I, I, I]
+        L.ranphy_cnn_workspace_bytes.restype = I64
+        L.ranphy_cnn_forward.argtypes = [P, P, P, ctypes.c_float, P, I, I, I, I, P, I64, P]
+        L.ranphy_cnn_grad.argtypes = [P, P, P, P, P, P, I, I, I, I, P, I64, P]
+        L.ranphy_cnn_adam.argtypes = [P, P, P, P, I, ctypes.c_float, P]
+        L.ranphy_cnn_denoise.argtypes = [D, P, P, ctypes.c_float, P, P, P, I64, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
-                  "ranphy_mmse_llr", "ranphy_llr_demap"):
+                  "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
+                  "ranphy_cnn_adam", "ranphy_cnn_denoise"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -221,3 +231,100 @@ def llr_demap(shape, x: torch.Tensor, nv: torch.Tensor, llr: Optional[torch.Tens
             _as_dev(llr, "llr", torch.float32, nl))
     _check("ranphy_llr_demap", lib().ranphy_llr_demap(ctypes.byref(d), *args, _stream(stream)))
     return llr
+
+
+# ---------------------------------------------------------------------------------------
+# Learned refinement of the pilot-resolution channel estimate (include/ranphy.h).
+# ---------------------------------------------------------------------------------------
+
+def cnn_param_count() -> int:
+    return int(lib().ranphy_cnn_param_count())
+
+
+def cnn_workspace_bytes(rows: int, cols: int, n_img: int, n_groups: int, train: bool) -> int:
+    n = int(lib().ranphy_cnn_workspace_bytes(rows, cols, n_img, n_groups, int(train)))
+    if n < 0:
+        raise ValueError(f"invalid denoiser dimensions: {status_str(n)}")
+    return n
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _f32(t: torch.Tensor, name: str, n: int) -> int:
+    return _as_dev(t, name, torch.float32, n)
+
+
+def cnn_forward(params: torch.Tensor, x: torch.Tensor, rows: int, cols: int, n_img: int,
+                n_groups: int, out: Optional[torch.Tensor] = None,
+                workspace: Optional[torch.Tensor] = None, noise_var: Optional[torch.Tensor] = None,
+                min_noise_var: float = 0.0, stream=None) -> torch.Tensor:
+    """The network on x [group][rows * cols][image][2] float32 (flat); with per-group noise
+    variances it refines noise-normalised estimates (out = x + sigma y) and groups below
+    min_noise_var keep x."""
+    n = n_groups * rows * cols * n_img * 2
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=x.device)
+    nb = cnn_workspace_bytes(rows, cols, n_img, n_groups, False)
+    ws = workspace if workspace is not None else _workspace(nb, x.device)
+    pn = None if noise_var is None else _f32(noise_var, "noise_var", n_groups)
+    _check("ranphy_cnn_forward", lib().ranphy_cnn_forward(
+        _f32(params, "params", cnn_param_count()), _f32(x, "x", n), pn, float(min_noise_var),
+        _f32(out, "out", n), rows, cols, n_img, n_groups, ws.data_ptr(), ws.numel(),
+        _stream(stream)))
+    return out
+
+
+def cnn_grad(params: torch.Tensor, x: torch.Tensor, target: torch.Tensor, rows: int, cols: int,
+             n_img: int, n_groups: int, grad: Optional[torch.Tensor] = None,
+             loss: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+             noise_var: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(loss, grad): the MSE loss of the network on x against target (in noise-normalised
+    units when noise variances are given) and its parameter gradient."""
+    n = n_groups * rows * cols * n_img * 2
+    if grad is None:
+        grad = torch.empty(cnn_param_count(), dtype=torch.float32, device=x.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    nb = cnn_workspace_bytes(rows, cols, n_img, n_groups, True)
+    ws = workspace if workspace is not None else _workspace(nb, x.device)
+    pn = None if noise_var is None else _f32(noise_var, "noise_var", n_groups)
+    _check("ranphy_cnn_grad", lib().ranphy_cnn_grad(
+        _f32(params, "params", cnn_param_count()), _f32(x, "x", n), _f32(target, "target", n),
+        pn, _f32(grad, "grad", cnn_param_count()), _f32(loss, "loss", 1), rows, cols, n_img,
+        n_groups, ws.data_ptr(), ws.numel(), _stream(stream)))
+    return loss, grad
+
+
+def cnn_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+             step: int, lr: float, stream=None) -> None:
+    n = cnn_param_count()
+    _check("ranphy_cnn_adam", lib().ranphy_cnn_adam(
+        _f32(params, "params", n), _f32(grad, "grad", n), _f32(m, "m", n), _f32(v, "v", n),
+        step, lr, _stream(stream)))
+
+
+def cnn_denoise(shape, params: torch.Tensor, h: torch.Tensor,
+                noise_var: Optional[torch.Tensor] = None, min_noise_var: float = 0.0,
+                out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """The trained network applied to a pilot-resolution estimate (returns the refined one).
+    Slots with noise_var below min_noise_var keep the plain estimate."""
+    d = desc_of(shape)
+    nh = buffer_floats(d, BUF_H, H_PILOT)
+    if out is None:
+        out = torch.empty(nh // 2, dtype=torch.complex64, device=h.device)
+    if workspace is None:
+        n_pilot = -(-shape.n_prb * 12 // shape.dmrs_comb)
+        nb = cnn_workspace_bytes(len(shape.dmrs_sym0), n_pilot, shape.n_rx * shape.n_layers,
+                                 max(1, min(shape.n_slots, 8)), False)
+        workspace = _workspace(nb, h.device)
+    pn = None if noise_var is None else _as_dev(noise_var, "noise_var", torch.float32,
+                                                buffer_floats(d, BUF_NOISE_VAR))
+    _check("ranphy_cnn_denoise", lib().ranphy_cnn_denoise(
+        ctypes.byref(d), _f32(params, "params", cnn_param_count()), pn, float(min_noise_var),
+        _as_dev(h, "h", torch.complex64, nh), _as_dev(out, "out", torch.complex64, nh),
+        workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return out

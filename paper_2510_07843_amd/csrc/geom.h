@@ -78,4 +78,18 @@ hipError_t launch_mmse_sc(const Geom& g, const float2* rx, const float2* h, int 
 hipError_t launch_llr_demap(const Geom& g, const float2* x, const float* nv, float* llr,
                             hipStream_t s);
 
+// The channel-estimate denoiser (cnn.hip).  Tensors [group][pixel][image][2] FP32.
+int64_t cnn_param_count();
+int64_t cnn_workspace_bytes(int rows, int cols, int nimg, int ngrp, bool train);
+// With per-group noise variances nv (may be null: none) the network refines noise-normalised
+// estimates, and groups with nv[g] < gate_min keep x.
+hipError_t cnn_forward(int rows, int cols, int nimg, int ngrp, const float* params,
+                       const float* x, float* out, void* ws, hipStream_t s,
+                       const float* nv = nullptr, float gate_min = 0.f);
+hipError_t cnn_grad(int rows, int cols, int nimg, int ngrp, const float* params, const float* x,
+                    const float* target, const float* nv, float* grad, float* loss, void* ws,
+                    hipStream_t s);
+hipError_t cnn_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                    hipStream_t s);
+
 }  // namespace ranphy

@@ -215,4 +215,94 @@ int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const float* nv,
                                                     llr, static_cast<hipStream_t>(stream)));
 }
 
+int64_t ranphy_cnn_param_count(void) { return ranphy::cnn_param_count(); }
+
+int64_t ranphy_cnn_workspace_bytes(int rows, int cols, int n_img, int n_groups, int train) {
+  if (rows < 1 || cols < 1 || n_img < 1 || n_groups < 0) return RANPHY_ERR_INVALID;
+  return ranphy::cnn_workspace_bytes(rows, cols, n_img, n_groups, train != 0);
+}
+
+static int cnn_check(int rows, int cols, int n_img, int n_groups, const void* ws,
+                     int64_t ws_bytes, int train) {
+  if (rows < 1 || cols < 1 || n_img < 1 || n_groups < 0) return RANPHY_ERR_INVALID;
+  if ((int64_t)rows * cols > (1 << 20) || n_img > (1 << 20)) return RANPHY_ERR_UNSUPPORTED;
+  if (ws == nullptr || ((uintptr_t)ws & 255u) ||
+      ws_bytes < ranphy::cnn_workspace_bytes(rows, cols, n_img, n_groups, train != 0))
+    return RANPHY_ERR_INVALID;
+  return RANPHY_OK;
+}
+
+static bool aligned4(const void* p) { return p != nullptr && ((uintptr_t)p & 3u) == 0; }
+
+int ranphy_cnn_forward(const float* params, const float* x, const float* noise_var,
+                       float min_noise_var, float* out, int rows, int cols, int n_img,
+                       int n_groups, void* workspace, int64_t workspace_bytes, void* stream) {
+  const int rc = cnn_check(rows, cols, n_img, n_groups, workspace, workspace_bytes, 0);
+  if (rc) return rc;
+  if (n_groups == 0) return RANPHY_OK;
+  if (!aligned4(params) || !ranphy::aligned8(x) || !ranphy::aligned8(out) ||
+      (noise_var != nullptr && !aligned4(noise_var)) || !(min_noise_var >= 0.f))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(ranphy::cnn_forward(rows, cols, n_img, n_groups, params, x, out,
+                                               workspace, static_cast<hipStream_t>(stream),
+                                               noise_var, min_noise_var));
+}
+
+int ranphy_cnn_grad(const float* params, const float* x, const float* target,
+                    const float* noise_var, float* grad, float* loss, int rows, int cols,
+                    int n_img, int n_groups, void* workspace, int64_t workspace_bytes,
+                    void* stream) {
+  const int rc = cnn_check(rows, cols, n_img, n_groups, workspace, workspace_bytes, 1);
+  if (rc) return rc;
+  if (n_groups < 1) return RANPHY_ERR_INVALID;
+  if (!aligned4(params) || !ranphy::aligned8(x) || !ranphy::aligned8(target) ||
+      !aligned4(grad) || !aligned4(loss) || (noise_var != nullptr && !aligned4(noise_var)))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(ranphy::cnn_grad(rows, cols, n_img, n_groups, params, x, target,
+                                            noise_var, grad, loss, workspace,
+                                            static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_cnn_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                    void* stream) {
+  if (!aligned4(params) || !aligned4(grad) || !aligned4(m) || !aligned4(v) || step < 1 ||
+      !(lr > 0.f))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(
+      ranphy::cnn_adam(params, grad, m, v, step, lr, static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const float* noise_var,
+                       float min_noise_var, const float* h_in, float* h_out, void* workspace,
+                       int64_t workspace_bytes, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (g.n_slots == 0) return RANPHY_OK;
+  const int rows = g.n_occ, cols = g.n_pilot, nimg = g.n_rx * g.n_layers;
+  if (workspace == nullptr || ((uintptr_t)workspace & 255u) || !aligned4(params) ||
+      !ranphy::aligned8(h_in) || !ranphy::aligned8(h_out) ||
+      (noise_var != nullptr && !aligned4(noise_var)) || !(min_noise_var >= 0.f))
+    return RANPHY_ERR_INVALID;
+  // as many slots per pass as the workspace holds
+  int chunk = 0;
+  for (int c = g.n_slots; c >= 1; c = c / 2) {
+    if (ranphy::cnn_workspace_bytes(rows, cols, nimg, c, false) <= workspace_bytes) {
+      chunk = c;
+      break;
+    }
+  }
+  if (chunk == 0) return RANPHY_ERR_INVALID;
+  const int64_t per_slot = (int64_t)rows * cols * nimg * 2;  // floats
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int s0 = 0; s0 < g.n_slots; s0 += chunk) {
+    const int n = g.n_slots - s0 < chunk ? g.n_slots - s0 : chunk;
+    const hipError_t e = ranphy::cnn_forward(
+        rows, cols, nimg, n, params, h_in + s0 * per_slot, h_out + s0 * per_slot, workspace, s,
+        noise_var != nullptr ? noise_var + s0 : nullptr, min_noise_var);
+    if (e != hipSuccess) return RANPHY_ERR_LAUNCH;
+  }
+  return RANPHY_OK;
+}
+
 }  // extern "C"

@@ -337,3 +337,98 @@ def make_batch(name: str, n_slots: Optional[int] = None, snr_db: Optional[Sequen
         out.update(bits=np.stack([t[0] for t in truth]), x=np.stack([t[1] for t in truth]),
                    h=np.stack([t[2] for t in truth]))
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# DMRS-only slots with a time-varying channel (training and test data of the learned
+# refinement of the pilot-resolution estimate).
+# ---------------------------------------------------------------------------------------
+
+def dmrs_shape(shape: SlotShape, n_slots: int) -> SlotShape:
+    """The DMRS occasion of `shape` alone: its T DMRS symbols at symbol 0 and one empty data
+    symbol (the smallest slot the library accepts)."""
+    return SlotShape(n_prb=shape.n_prb, n_symb=shape.dmrs_td + 1, n_rx=shape.n_rx,
+                     n_layers=shape.n_layers, qm=shape.qm, dmrs_comb=shape.dmrs_comb,
+                     dmrs_td=shape.dmrs_td, dmrs_sym0=(0,), n_slots=n_slots)
+
+
+def make_dmrs_slot(shape: SlotShape, rng: np.random.Generator, scs_hz: float, tau_rms: float,
+                   doppler_hz: float, snr_db: float, n_sinusoids: int = 16):
+    """One DMRS occasion (shape = dmrs_shape(..)) through a TDL channel with an exponential
+    PDP of rms delay spread tau_rms whose taps change over the occasion's T symbols with
+    maximum Doppler shift doppler_hz (each tap of each (rx, port) link a sum of n_sinusoids
+    complex sinusoids of frequency doppler_hz cos(alpha) with random alpha and phase: a
+    Jakes-type spectrum, unit power).
+
+    Returns rx [symb][sc][rx] complex64 (data symbol empty), pilots [1][T][J][layer]
+    complex64, h [1][J][rx][layer] complex64: the true channel at port layer's pilot
+    subcarrier (layer mod C) + C j averaged over the T DMRS symbols (zero where that
+    subcarrier is past the band), noise_var.
+    """
+    C, T, J = shape.dmrs_comb, shape.dmrs_td, shape.n_pilot
+    NR, NL, nsc = shape.n_rx, shape.n_layers, shape.n_sc
+    pilots = make_pilots(rng, shape)
+    delays, powers = power_delay_profile(("exp", tau_rms), scs_hz)
+    nt = len(delays)
+    t_sym = 1.0 / scs_hz * (1.0 + 144.0 / 2048.0)  # OFDM symbol with its normal cyclic prefix
+    alpha = rng.uniform(0, 2 * np.pi, (nt, NR, NL, n_sinusoids))
+    phi = rng.uniform(0, 2 * np.pi, (nt, NR, NL, n_sinusoids))
+    t = np.arange(T) * t_sym
+    g = np.exp(1j * (2 * np.pi * doppler_hz * np.cos(alpha)[..., None] * t + phi[..., None]))
+    g = g.sum(axis=3) * np.sqrt(powers / n_sinusoids)[:, None, None, None]  # [tap][rx][port][t]
+    k = (np.arange(NL)[None, :] % C) + C * np.arange(J)[:, None]  # [j][port]
+    steer = np.exp(-2j * np.pi * scs_hz * k[..., None] * delays)   # [j][port][tap]
+    Ht = np.einsum("jpn,nrpt->tjrp", steer, g)                     # [t][j][rx][port]
+    inband = (k < nsc)[None, :, None, :]
+    Ht = np.where(inband, Ht, 0)
+    y = np.zeros((shape.n_symb, nsc, NR), np.complex128)
+    for p in range(NL):
+        ks = k[:, p]
+        ok = ks < nsc
+        for tt in range(T):
+            y[tt, ks[ok], :] += Ht[tt, ok, :, p] * pilots[0, tt, ok, p][:, None]
+    noise_var = 10.0 ** (-snr_db / 10.0)
+    y = y.astype(np.complex64)
+    y[:T] += awgn(rng, (T, nsc, NR), noise_var)
+    h = Ht.mean(axis=0).astype(np.complex64)[None]
+    return dict(rx=y, pilots=pilots, h=h, noise_var=float(noise_var))
+
+
+# Training / test draws of the refinement: per slot a delay spread in 30..300 ns, a maximum
+# Doppler shift in 0..500 Hz and an SNR in 0..30 dB, uniformly.
+DMRS_RANGES = dict(tau_rms=(30e-9, 300e-9), doppler_hz=(0.0, 500.0), snr_db=(0.0, 30.0))
+
+
+def make_dmrs_batch(shape: SlotShape, n_slots: int, seed: int, scs_hz: float = 30e3,
+                    snr_db: Optional[Sequence[float]] = None, tau_rms: Optional[float] = None,
+                    doppler_hz: Optional[float] = None, workers: int = 1):
+    """n_slots DMRS occasions, slot i from its own stream SeedSequence([root, 7, seed, i]);
+    fixed snr_db (cycled), tau_rms or doppler_hz replace the uniform draws."""
+    sh = dmrs_shape(shape, n_slots)
+    rx = np.empty((n_slots, sh.n_symb, sh.n_sc, sh.n_rx), np.complex64)
+    pil = np.empty((n_slots, 1, sh.dmrs_td, sh.n_pilot, sh.n_layers), np.complex64)
+    h = np.empty((n_slots, 1, sh.n_pilot, sh.n_rx, sh.n_layers), np.complex64)
+    nv = np.empty(n_slots, np.float32)
+    draws = np.empty((n_slots, 3))
+
+    def one(i):
+        rng = rng_for(7, seed, i)
+        u = rng.uniform(size=3)
+        lo = DMRS_RANGES
+        ds = tau_rms if tau_rms is not None else lo["tau_rms"][0] + u[0] * (lo["tau_rms"][1] - lo["tau_rms"][0])
+        fd = doppler_hz if doppler_hz is not None else lo["doppler_hz"][0] + u[1] * (lo["doppler_hz"][1] - lo["doppler_hz"][0])
+        snr = (snr_db[i % len(snr_db)] if snr_db is not None
+               else lo["snr_db"][0] + u[2] * (lo["snr_db"][1] - lo["snr_db"][0]))
+        d = make_dmrs_slot(sh, rng, scs_hz, ds, fd, snr)
+        rx[i], pil[i], h[i], nv[i] = d["rx"], d["pilots"], d["h"], d["noise_var"]
+        draws[i] = (ds, fd, snr)
+
+    if workers > 1:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(n_slots)))
+    else:
+        for i in range(n_slots):
+            one(i)
+    return dict(shape=sh, rx=rx, pilots=pil, h=h, noise_var=nv, tau_rms=draws[:, 0],
+                doppler_hz=draws[:, 1], snr_db=draws[:, 2])

@@ -1,0 +1,259 @@
+"""GPU parity of the learned channel-estimate refinement against the FP64 oracle
+(oracle/cnn_ref.py), and what the network trained on the GPU gains over the plain estimate.
+
+Bars (BF16 operands and activations, FP32 accumulation; the oracle runs in FP64 on the same
+BF16-rounded weights and inputs):
+  * forward: |out_gpu - out_ref| <= 3e-2 max|y_ref| per element and the rms error <= 1e-2
+    rms(y_ref), y = out - x the network's part (each of the three hidden activations is
+    rounded to BF16, relative 2^-9);
+  * gradients: per tensor ||g_gpu - g_ref|| <= 5e-2 ||g_ref|| (BF16 activations and BF16
+    output gradients), loss within 1e-2 relative; padded channels exactly zero.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2510_07843_amd as ranphy
+import synth
+from oracle import cnn_ref as C
+
+pytestmark = pytest.mark.gpu
+
+NP = 36992  # 4 layers x (9 x 32 x 32 + 32)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ranphy.lib()
+    assert ranphy.cnn_param_count() == NP
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_round(a):
+    """Round to the nearest BF16 value (ties to even), returned as float32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def pack(p):
+    out = np.zeros(NP, np.float32)
+    for l in range(4):
+        W = np.zeros((9, 32, 32))
+        ci, co = p[f"W{l}"].shape[1:]
+        W[:, :ci, :co] = p[f"W{l}"]
+        b = np.zeros(32)
+        b[:co] = p[f"b{l}"]
+        out[l * 9248:l * 9248 + 9216] = W.reshape(-1)
+        out[l * 9248 + 9216:(l + 1) * 9248] = b
+    return out
+
+
+def unpack(v):
+    p = {}
+    for l in range(4):
+        ci, co = C.CHANNELS[l], C.CHANNELS[l + 1]
+        p[f"W{l}"] = v[l * 9248:l * 9248 + 9216].reshape(9, 32, 32)[:, :ci, :co].astype(np.float64)
+        p[f"b{l}"] = v[l * 9248 + 9216:(l + 1) * 9248][:co].astype(np.float64)
+    return p
+
+
+def test_padded_entries_of_the_packing():
+    v = pack(C.init_params(np.random.default_rng(0)))
+    W0 = v[:9216].reshape(9, 32, 32)
+    assert not W0[:, 2:, :].any()
+    W3 = v[3 * 9248:3 * 9248 + 9216].reshape(9, 32, 32)
+    assert not W3[:, :, 2:].any() and not v[3 * 9248 + 9216 + 2:].any()
+
+
+def net_params(seed):
+    rng = np.random.default_rng(seed)
+    p = C.init_params(rng)
+    p["W3"] *= 10.0
+    for l in range(4):
+        p[f"b{l}"] = 0.05 * rng.standard_normal(p[f"b{l}"].shape)
+    # the network as the GPU holds it: BF16 weights, FP32 biases
+    for l in range(4):
+        p[f"W{l}"] = bf16_round(p[f"W{l}"]).astype(np.float64)
+    return p
+
+
+GRIDS = [(1, 37, 20, 2), (2, 13, 16, 1), (3, 5, 33, 1), (1, 410, 64, 1)]
+
+
+@pytest.mark.parametrize("rows,cols,nimg,ngrp", GRIDS)
+def test_forward_matches_oracle(rows, cols, nimg, ngrp):
+    say(f"cnn forward {rows}x{cols}, {nimg} images, {ngrp} groups")
+    p = net_params(rows * 100 + cols)
+    rng = np.random.default_rng(cols)
+    x = bf16_round(rng.standard_normal((ngrp, rows * cols, nimg, 2)))
+    out = ranphy.cnn_forward(torch.from_numpy(pack(p)).cuda(),
+                             torch.from_numpy(x.reshape(-1)).cuda(), rows, cols, nimg, ngrp)
+    og = out.cpu().numpy().reshape(x.shape)
+    for g in range(ngrp):
+        ref, _ = C.forward(x[g].astype(np.float64), p, rows, cols)
+        y = ref - x[g]
+        err = np.abs(og[g] - ref)
+        say(f"  group {g}: max err {err.max():.3e} (max |y| {np.abs(y).max():.3e}), "
+            f"rms err / rms y {np.sqrt(np.mean(err ** 2) / np.mean(y ** 2)):.3e}")
+        assert err.max() <= 3e-2 * np.abs(y).max()
+        assert np.sqrt(np.mean(err ** 2)) <= 1e-2 * np.sqrt(np.mean(y ** 2))
+
+
+@pytest.mark.parametrize("rows,cols,nimg,ngrp", [(1, 37, 20, 2), (2, 13, 16, 1), (1, 130, 80, 1)])
+def test_gradients_match_oracle(rows, cols, nimg, ngrp):
+    say(f"cnn gradients {rows}x{cols}, {nimg} images, {ngrp} groups")
+    p = net_params(7 + rows + cols)
+    rng = np.random.default_rng(nimg)
+    x = bf16_round(rng.standard_normal((ngrp, rows * cols, nimg, 2)))
+    target = rng.standard_normal(x.shape).astype(np.float32)
+    loss, grad = ranphy.cnn_grad(torch.from_numpy(pack(p)).cuda(),
+                                 torch.from_numpy(x.reshape(-1)).cuda(),
+                                 torch.from_numpy(target.reshape(-1)).cuda(), rows, cols, nimg, ngrp)
+    torch.cuda.synchronize()
+    gv = grad.cpu().numpy()
+    # the oracle over all groups at once: groups are independent images on the same grid
+    xa = np.concatenate([x[g] for g in range(ngrp)], axis=1).astype(np.float64)
+    ta = np.concatenate([target[g] for g in range(ngrp)], axis=1).astype(np.float64)
+    Lr, gr = C.loss_and_grads(xa, ta, p, rows, cols)
+    say(f"  loss gpu {loss.item():.6f} oracle {Lr:.6f}")
+    assert abs(loss.item() - Lr) <= 1e-2 * Lr
+    gg = unpack(gv)
+    for name in sorted(gr):
+        rel = np.linalg.norm(gg[name] - gr[name]) / np.linalg.norm(gr[name])
+        say(f"  {name}: relative error {rel:.3e}")
+        assert rel <= 5e-2, name
+    # padded channels carry exactly zero gradient
+    full = pack({k: v for k, v in gg.items()})
+    assert np.array_equal(gv[:9216].reshape(9, 32, 32)[:, 2:, :], np.zeros((9, 30, 32)))
+    W3 = gv[3 * 9248:3 * 9248 + 9216].reshape(9, 32, 32)
+    assert not W3[:, :, 2:].any() and not gv[3 * 9248 + 9216 + 2:].any()
+    assert np.array_equal(full, gv)
+
+
+def test_noise_normalised_forward_and_gradients():
+    # With per-group noise variances the network sees x / sigma and refines x into x + sigma y;
+    # the loss compares x / sigma + y with target / sigma.  The oracle runs on the normalised
+    # tensors; groups with a noise variance below the gate keep x exactly.
+    rows, cols, nimg, ngrp = 1, 41, 24, 3
+    p = net_params(99)
+    rng = np.random.default_rng(98)
+    nv = np.array([0.5, 2e-3, 1e-5], np.float32)
+    sig = np.sqrt(nv.astype(np.float64))
+    x = rng.standard_normal((ngrp, rows * cols, nimg, 2)).astype(np.float32)
+    target = rng.standard_normal(x.shape).astype(np.float32)
+    pd, xd, nd = (torch.from_numpy(a).cuda() for a in (pack(p), x.reshape(-1), nv))
+    out = ranphy.cnn_forward(pd, xd, rows, cols, nimg, ngrp, noise_var=nd, min_noise_var=1e-4)
+    og = out.cpu().numpy().reshape(x.shape)
+    assert np.array_equal(og[2], x[2])  # below the gate
+    for g in range(2):
+        xn = bf16_round(x[g] / np.float32(sig[g])).astype(np.float64)
+        ref, _ = C.forward(xn, p, rows, cols)
+        y = ref - xn
+        err = np.abs((og[g] - x[g]) / sig[g] - y)  # the network part in normalised units
+        say(f"  group {g}: max err {err.max():.3e} (max |y| {np.abs(y).max():.3e})")
+        assert err.max() <= 3e-2 * np.abs(y).max()
+    loss, grad = ranphy.cnn_grad(pd, xd, torch.from_numpy(target.reshape(-1)).cuda(), rows, cols,
+                                 nimg, ngrp, noise_var=nd)
+    xa = np.concatenate([x[g] / sig[g] for g in range(ngrp)], axis=1)
+    ta = np.concatenate([target[g] / sig[g] for g in range(ngrp)], axis=1)
+    Lr, gr = C.loss_and_grads(bf16_round(xa).astype(np.float64), ta, p, rows, cols)
+    say(f"  loss gpu {loss.item():.6f} oracle {Lr:.6f}")
+    assert abs(loss.item() - Lr) <= 1e-2 * Lr
+    gg = unpack(grad.cpu().numpy())
+    for name in sorted(gr):
+        rel = np.linalg.norm(gg[name] - gr[name]) / np.linalg.norm(gr[name])
+        say(f"  {name}: relative error {rel:.3e}")
+        assert rel <= 5e-2, name
+
+
+def test_adam_learns_a_smoothing_map():
+    # Target: the input averaged with its two row neighbours, a map the network can represent.
+    rows, cols, nimg = 1, 64, 64
+    rng = np.random.default_rng(5)
+    x = bf16_round(rng.standard_normal((1, rows * cols, nimg, 2)))
+    xp = np.pad(x, ((0, 0), (1, 1), (0, 0), (0, 0)))
+    target = ((xp[:, :-2] + xp[:, 1:-1] + xp[:, 2:]) / 3).astype(np.float32)
+    params = torch.from_numpy(pack(C.init_params(np.random.default_rng(6)))).cuda()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    xd, td = torch.from_numpy(x.reshape(-1)).cuda(), torch.from_numpy(target.reshape(-1)).cuda()
+    losses = []
+    for step in range(1, 201):
+        loss, grad = ranphy.cnn_grad(params, xd, td, rows, cols, nimg, 1)
+        ranphy.cnn_adam(params, grad, m, v, step, 2e-3)
+        if step in (1, 200):
+            losses.append(loss.item())
+    say(f"adam: loss {losses[0]:.4f} -> {losses[1]:.4f}")
+    assert losses[1] < 0.1 * losses[0]
+
+
+def nmse_db(est, h):
+    return 10 * np.log10(np.sum(np.abs(est - h) ** 2) / np.sum(np.abs(h) ** 2))
+
+
+def ls_estimate(batch):
+    sh = batch["shape"]
+    return ranphy.chest_ls(sh, torch.from_numpy(batch["rx"]).cuda().reshape(-1),
+                           torch.from_numpy(batch["pilots"]).cuda().reshape(-1))
+
+
+def test_trained_denoiser_beats_plain_estimate():
+    # 16 Rx x 16 layers over 273 PRB (comb 8, double-symbol cover: 410 pilots per port), the
+    # 64 x 16 workload's pilot grid.  Train on the GPU (300 Adam steps, 4 slots of 256 images
+    # a step) on 160 slots drawn with delay spread 30..300 ns, Doppler 0..500 Hz and SNR
+    # 0..30 dB; choose the noise-variance gate on validation slots; then judge the NMSE of the
+    # pilot-resolution estimate on held-out test slots against the plain LS estimate.
+    from paper_2510_07843_amd import denoise
+    base = synth.SlotShape(273, 14, 16, 16, 6, 8, 2, (2,), 1)
+    train = synth.make_dmrs_batch(base, 160, seed=11, workers=8)
+    sh = train["shape"]
+    nimg, cols = sh.n_rx * sh.n_layers, sh.n_pilot
+    res = denoise.train(ls_estimate(train), torch.from_numpy(train["h"]).cuda(),
+                        torch.from_numpy(train["noise_var"]).cuda(), sh.n_slots, 1, cols, nimg,
+                        steps=300, batch=4, seed=12)
+    say(f"trained {res['steps']} steps in {res['seconds']:.2f} s; loss every 100 steps "
+        f"{res['losses'][9]:.5f} {res['losses'][19]:.5f} {res['losses'][29]:.5f}")
+    params = res["params"]
+    grid = (0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0)
+    val = synth.make_dmrs_batch(base, 2 * len(grid), seed=31, snr_db=grid, workers=8)
+    gate = denoise.choose_gate(params, ls_estimate(val), torch.from_numpy(val["h"]).cuda(),
+                               torch.from_numpy(val["noise_var"]).cuda(), val["snr_db"], 1, cols,
+                               nimg)
+    say(f"validation: {gate['nmse']}; refine up to {gate['max_snr_db']} dB")
+    assert gate["max_snr_db"] is not None and gate["max_snr_db"] >= 10.0
+
+    snrs = (0.0, 10.0, 20.0, 30.0)
+    test = synth.make_dmrs_batch(base, 4 * len(snrs), seed=21, snr_db=snrs, workers=8)
+    ts = test["shape"]
+    h_ls = ls_estimate(test)
+    nv = torch.from_numpy(test["noise_var"]).cuda()
+    h_cnn = ranphy.cnn_denoise(ts, params, h_ls, noise_var=nv, min_noise_var=gate["min_noise_var"])
+    h_all = ranphy.cnn_denoise(ts, params, h_ls, noise_var=nv)  # no gate: every slot refined
+    # the batched entry point is the network applied slot by slot
+    x_test = torch.view_as_real(h_ls).reshape(-1).contiguous()
+    ref = ranphy.cnn_forward(params, x_test, 1, cols, nimg, ts.n_slots, noise_var=nv)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(h_all).reshape(-1), ref)
+    shp = test["h"].shape
+    ls, cnn, full = (t.cpu().numpy().reshape(shp) for t in (h_ls, h_cnn, h_all))
+    gated = test["noise_var"] < gate["min_noise_var"]
+    assert np.array_equal(cnn[gated], ls[gated])  # gated slots keep the plain estimate exactly
+    assert np.array_equal(cnn[~gated], full[~gated])
+    gains = {}
+    for snr in snrs:
+        sel = test["snr_db"] == snr
+        a, b, c = (nmse_db(e[sel], test["h"][sel]) for e in (ls, full, cnn))
+        gains[snr] = a - c
+        say(f"SNR {snr:4.1f} dB: NMSE plain {a:7.2f} dB, refined {b:7.2f} dB, "
+            f"gated {c:7.2f} dB (gain {a - c:+.2f} dB)")
+    assert gains[0.0] >= 3.0 and gains[10.0] >= 2.0
+    assert gains[30.0] >= -0.1
