@@ -207,6 +207,68 @@ def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, fused, scs_hz
             "data_re_per_slot": one.n_dsym * one.n_sc}
 
 
+def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96):
+    """Train the pilot-estimate refinement on the GPU for the workload's DMRS grid (delay
+    spread 30..300 ns, Doppler 0..500 Hz, SNR 0..30 dB) and choose its noise-variance gate on
+    validation slots at the largest delay spread of that range (the conservative judge: the
+    refinement is kept only at SNRs where it helps the most frequency-selective channels it
+    was trained for); returns the parameters, the gate and a report."""
+    from paper_2510_07843_amd import denoise
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    tr = synth.make_dmrs_batch(shape, n_train, seed=41, workers=min(16, os.cpu_count() or 1))
+    grid = (0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0)
+    va = synth.make_dmrs_batch(shape, 2 * len(grid), seed=42, snr_db=grid,
+                               tau_rms=synth.DMRS_RANGES["tau_rms"][1],
+                               workers=min(16, os.cpu_count() or 1))
+    t_gen = time.perf_counter() - t0
+    ts = tr["shape"]
+    cols, nimg = ts.n_pilot, ts.n_rx * ts.n_layers
+
+    def ls(b):
+        return ranphy.chest_ls(b["shape"], torch.from_numpy(b["rx"]).to(dev).reshape(-1),
+                               torch.from_numpy(b["pilots"]).to(dev).reshape(-1))
+
+    res = denoise.train(ls(tr), torch.from_numpy(tr["h"]).to(dev),
+                        torch.from_numpy(tr["noise_var"]).to(dev), n_train, 1, cols, nimg,
+                        steps=steps, batch=batch, seed=43)
+    gate = denoise.choose_gate(res["params"], ls(va), torch.from_numpy(va["h"]).to(dev),
+                               torch.from_numpy(va["noise_var"]).to(dev), va["snr_db"], 1, cols,
+                               nimg)
+    report = {"train_slots": n_train, "images_per_slot": nimg, "steps": steps,
+              "images_per_step": res["images_per_step"], "train_seconds": round(res["seconds"], 2),
+              "data_seconds": round(t_gen, 1), "loss_first_last": [res["losses"][0], res["losses"][-1]],
+              "refine_up_to_snr_db": gate["max_snr_db"], "validation_nmse": gate["nmse"]}
+    return res["params"], gate["min_noise_var"], report
+
+
+def learned_quality(torch, ranphy, synth, params, min_nv):
+    """Post-equalisation SINR with the refined estimate and with the plain one (FP32
+    detector) on one slot per SNR point of the 64 x 16 workload."""
+    t = synth.make_batch("m", n_slots=len(synth.CONFIGS["m"]["snr_db"]), workers=8)
+    sh = t["shape"]
+    dev = torch.device("cuda:0")
+    rx = torch.from_numpy(t["rx"]).to(dev).reshape(-1)
+    pil = torch.from_numpy(t["pilots"]).to(dev).reshape(-1)
+    nvar = torch.from_numpy(t["noise_var"]).to(dev)
+
+    def sinr(xh, x):
+        return 10 * np.log10(np.mean(np.abs(x) ** 2) / np.mean(np.abs(xh - x) ** 2))
+
+    hg = ranphy.chest_ls(sh, rx, pil)
+    hr = ranphy.cnn_denoise(sh, params, hg, noise_var=nvar, min_noise_var=min_nv)
+    out = {}
+    for name, h in (("plain", hg), ("refined", hr)):
+        xg, _ = ranphy.mmse_detect(sh, rx, h, nvar)
+        torch.cuda.synchronize()
+        xg = xg.cpu().numpy().reshape(t["x"].shape)
+        out[name] = [sinr(xg[i], t["x"][i]) for i in range(sh.n_slots)]
+    return {"snr_db": [float(v) for v in t["snr_db"]],
+            "sinr_plain_db": [round(v, 3) for v in out["plain"]],
+            "sinr_refined_db": [round(v, 3) for v in out["refined"]],
+            "sinr_gain_db": [round(b - a, 3) for a, b in zip(out["plain"], out["refined"])]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +288,8 @@ def main():
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the one-slot latency runs (profiled runs: they launch the same "
                          "kernels at one-slot size)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and timing the learned estimate refinement")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16/BF16 detector runs and the SINR comparison")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
@@ -272,26 +336,35 @@ def main():
 
     fused = fused_eligible(shape) if args.path == "auto" else args.path == "fused"
 
-    def run_timed(precision, fused):
-        """Warm up, then time exactly args.steps steps; returns (ms per step, per-kernel ms)."""
+    def run_timed(precision, fused, refine=None):
+        """Warm up, then time exactly args.steps steps; returns (ms per step, per-kernel ms).
+        refine = (params, min_noise_var, workspace) inserts the learned estimate refinement."""
         names = ("chest_ls", "mmse_llr") if fused else ("chest_ls", "mmse_detect", "llr_demap")
+        if refine is not None:
+            names = names[:1] + ("cnn_denoise",) + names[1:]
         ev = {n: [] for n in names}
 
         def step(record):
             marks = ([torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
                      if record else None)
+            base = 2 if refine is not None else 1  # mark index after the steps before detection
             if record:
                 marks[0].record()
             ranphy.chest_ls(shape, rx, pil, h=h, h_res=h_res)
             if record:
                 marks[1].record()
+            if refine is not None:
+                ranphy.cnn_denoise(shape, refine[0], h, noise_var=nvar, min_noise_var=refine[1],
+                                   out=h, workspace=refine[2])
+                if record:
+                    marks[2].record()
             if fused:
                 ranphy.mmse_llr(shape, rx, h, nvar, h_res=h_res, llr=llr, precision=precision)
             else:
                 ranphy.mmse_detect(shape, rx, h, nvar, h_res=h_res, x=x, nv=nv,
                                    precision=precision)
                 if record:
-                    marks[2].record()
+                    marks[base + 1].record()
                 ranphy.llr_demap(shape, x, nv, llr=llr)
             if record:
                 marks[-1].record()
@@ -377,6 +450,16 @@ def main():
                 variants[key] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
                                  "kernels_ms": v_k}
                 variants[key].update(quality[name])
+        if not args.no_learned:
+            params, min_nv, report = train_refinement(torch, ranphy, synth, shape)
+            nimg = shape.n_rx * shape.n_layers
+            wsb = ranphy.cnn_workspace_bytes(shape.n_occ, shape.n_pilot, nimg,
+                                             min(shape.n_slots, 35), False)
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+            v_ms, v_k = run_timed(ranphy.PREC_FP32, fused, refine=(params, min_nv, ws))
+            variants["learned_fp32"] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
+                                        "kernels_ms": v_k, "training": report}
+            variants["learned_fp32"].update(learned_quality(torch, ranphy, synth, params, min_nv))
         out["variants"] = variants
         out["variants_note"] = ("Gram and matched filter with FP32 / FP16 / BF16 inputs (FP32 "
                                 "accumulation, FP32 inversion), demapping fused into the "
