@@ -237,6 +237,34 @@ RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params
                                   const float* h_in, float* h_out, void* workspace,
                                   int64_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Many UEs of uneven allocations in one persistent launch (the scheduling and divergence
+ * costs of SIMT processing the paper weighs in Sec. V): for every UE, LS estimation at the
+ * pilots, interpolation, LMMSE detection and max-log demapping, LLRs out.
+ *
+ * ranphy_batch_plan builds, on the host, a plan of the batch (per UE its geometry and
+ * buffers, and work items of about `tile_re` resource elements each: tiles of consecutive
+ * subcarriers, grouped by (layers, modulation, antennas) class, heaviest first) and copies it
+ * synchronously into `plan`, device memory of ranphy_batch_plan_bytes(..) bytes, 256-byte
+ * aligned, owned by the caller.  The UE buffers must stay valid while the plan is used; their
+ * contents may change between runs.  ranphy_batch_run clears the plan's work counter and
+ * launches `n_blocks` persistent blocks of 256 threads on `stream` that take items until none
+ * is left (both launches can be captured into a HIP graph; runs of one plan must not
+ * overlap).  Per UE: one slot (desc.n_slots = 1), 1..8 layers; LLRs as ranphy_llr_demap.
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+  ranphy_slot_desc desc;  /* the UE's allocation, n_slots = 1 */
+  const float* rx;        /* [symb][sc][rx] complex64 */
+  const float* pilots;    /* [occ][t][j][layer] complex64 */
+  const float* noise_var; /* one float */
+  float* llr;             /* [dsym][sc][layer][qm] float */
+} ranphy_ue;
+
+RANPHY_API int64_t ranphy_batch_plan_bytes(const ranphy_ue* ues, int n_ue, int tile_re);
+RANPHY_API int ranphy_batch_plan(const ranphy_ue* ues, int n_ue, int tile_re, void* plan,
+                                 int64_t plan_bytes);
+RANPHY_API int ranphy_batch_run(void* plan, int n_blocks, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,7 @@ EXPORTED_SYMBOLS = (
     "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_mmse_llr",
     "ranphy_llr_demap", "ranphy_cnn_param_count", "ranphy_cnn_workspace_bytes",
     "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
+    "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run",
 )
 
 
@@ -58,6 +59,13 @@ class SlotDesc(ctypes.Structure):
             d.dmrs_sym0[i] = s
         d.n_slots = n_slots
         return d
+
+
+class UeRec(ctypes.Structure):
+    """Mirror of ``ranphy_ue``."""
+
+    _fields_ = [("desc", SlotDesc), ("rx", ctypes.c_void_p), ("pilots", ctypes.c_void_p),
+                ("noise_var", ctypes.c_void_p), ("llr", ctypes.c_void_p)]
 
 
 def desc_of(shape) -> SlotDesc:
@@ -99,9 +107,15 @@ def lib() -> ctypes.CDLL:
         L.ranphy_cnn_grad.argtypes = [P, P, P, P, P, P, I, I, I, I, P, I64, P]
         L.ranphy_cnn_adam.argtypes = [P, P, P, P, I, ctypes.c_float, P]
         L.ranphy_cnn_denoise.argtypes = [D, P, P, ctypes.c_float, P, P, P, I64, P]
+        UE = ctypes.POINTER(UeRec)
+        L.ranphy_batch_plan_bytes.argtypes = [UE, I, I]
+        L.ranphy_batch_plan_bytes.restype = I64
+        L.ranphy_batch_plan.argtypes = [UE, I, I, P, I64]
+        L.ranphy_batch_run.argtypes = [P, I, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
                   "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
-                  "ranphy_cnn_adam", "ranphy_cnn_denoise"):
+                  "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_batch_plan",
+                  "ranphy_batch_run"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -328,3 +342,42 @@ def cnn_denoise(shape, params: torch.Tensor, h: torch.Tensor,
         _as_dev(h, "h", torch.complex64, nh), _as_dev(out, "out", torch.complex64, nh),
         workspace.data_ptr(), workspace.numel(), _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# Many UEs in one persistent launch (include/ranphy.h).
+# ---------------------------------------------------------------------------------------
+
+class Batch:
+    """A plan over UEs, each a dict with ``shape`` (one slot) and GPU tensors ``rx``,
+    ``pilots``, ``noise_var`` (one value) and ``llr`` (allocated when missing).  The tensors
+    are kept alive with the plan; their contents may change between runs."""
+
+    def __init__(self, ues, tile_re: int = 512):
+        self.ues = ues
+        recs = (UeRec * len(ues))()
+        for i, u in enumerate(ues):
+            sh = u["shape"]
+            d = desc_of(sh)
+            if "llr" not in u or u["llr"] is None:
+                u["llr"] = torch.empty(buffer_floats(d, BUF_LLR), dtype=torch.float32,
+                                       device=u["rx"].device)
+            recs[i].desc = d
+            recs[i].rx = _as_dev(u["rx"], "rx", torch.complex64, buffer_floats(d, BUF_RX))
+            recs[i].pilots = _as_dev(u["pilots"], "pilots", torch.complex64,
+                                     buffer_floats(d, BUF_PILOTS))
+            recs[i].noise_var = _as_dev(u["noise_var"], "noise_var", torch.float32, 1)
+            recs[i].llr = _as_dev(u["llr"], "llr", torch.float32, buffer_floats(d, BUF_LLR))
+        self._recs = recs
+        self.tile_re = tile_re
+        n = int(lib().ranphy_batch_plan_bytes(recs, len(ues), tile_re))
+        if n < 0:
+            raise RanphyError("ranphy_batch_plan_bytes", n)
+        self.plan = torch.empty(n, dtype=torch.uint8, device=ues[0]["rx"].device)
+        _check("ranphy_batch_plan", lib().ranphy_batch_plan(recs, len(ues), tile_re,
+                                                            self.plan.data_ptr(), n))
+        self.n_items = int(self.plan[4:8].cpu().view(torch.int32).item())
+
+    def run(self, n_blocks: int, stream=None) -> None:
+        _check("ranphy_batch_run", lib().ranphy_batch_run(self.plan.data_ptr(), n_blocks,
+                                                          _stream(stream)))

@@ -1,0 +1,285 @@
+// Many UEs of uneven allocations in one persistent launch: LS estimation, interpolation,
+// LMMSE detection and max-log demapping for every UE of a batch.  The paper names divergence
+// and scheduling overhead as the weak points of SIMT processing for PHY work (Sec. V); here
+// the launch does not depend on the batch's composition and the work is dealt out in
+// homogeneous pieces.
+//
+// A plan (built on the host, resident in device memory) holds one record per UE (its
+// geometry and buffers) and a list of work items, each a tile of consecutive subcarriers of
+// one UE, sorted so that items of one class (layers, modulation, antennas) are adjacent and
+// the heaviest come first.  Every block of the persistent grid takes the next item from an
+// atomic counter until the list is exhausted, so the grid is as large as the chip holds and
+// no more; a one-thread kernel clears the counter before each run (both capture into a HIP
+// graph).  An item is processed by one block without depending on any other:
+//   1. the LS estimate (Sec. III-B: channel estimation) of every pilot the tile's
+//      subcarriers interpolate from, per occasion, into LDS;
+//   2. per resource element of the tile (all data symbols): frequency and time
+//      interpolation from LDS, Gram and matched filter streamed over the receive antennas,
+//      Cholesky factorisation and forward / backward substitution (Sec. IV, Fig. 4),
+//      unbiasing, and the max-log LLRs written to the UE's output.
+// Layers 1..8 (a template parameter: one branch per item, uniform over the block),
+// antennas 1..64, every modulation and DMRS configuration of the library.
+#include <float.h>
+
+#include "batch.h"
+#include "llr_math.h"
+
+namespace ranphy {
+
+namespace {
+
+constexpr float kPivotRel = 16.f * FLT_EPSILON;
+
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// LLRs of one layer of one RE (compile-time Qm: the values stay in registers).
+template <int QM>
+__device__ __forceinline__ void demap_store(float* __restrict__ dst, float2 xo, float vo) {
+  float out[QM];
+  llr_one<QM>(xo, vo, out);
+#pragma unroll
+  for (int b = 0; b < QM; b += 2)
+    *reinterpret_cast<float2*>(dst + b) = make_float2(out[b], out[b + 1]);
+}
+
+template <int NL>
+__device__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+                            const float2* __restrict__ lds) {
+  const int NR = g.n_rx, ND = g.n_dsym;
+  const float s2 = *u.nv;
+  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
+    const int d = e / nk;
+    const int k = k0 + (e - d * nk);
+    const int s = g.dsym[d];
+    const int o0 = g.t_o0[d], o1 = g.t_o1[d];
+    const float w = g.t_w[d];
+    int r0[NL], r1[NL];
+    float a[NL];
+#pragma unroll
+    for (int p = 0; p < NL; ++p) {
+      int j0, j1;
+      freq_rule(g, p, k, j0, j1, a[p]);
+      r0[p] = j0 - jlo;
+      r1[p] = j1 - jlo;
+    }
+    constexpr int NP = NL * (NL + 1) / 2;
+    float2 G[NP], z[NL];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) G[i] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
+    const float2* __restrict__ yrow = u.rx + ((int64_t)s * g.n_sc + k) * NR;
+    for (int r = 0; r < NR; ++r) {
+      float2 hr[NL];
+#pragma unroll
+      for (int p = 0; p < NL; ++p) {
+        const float2* b = lds + r * NL + p;
+        const float2 v0 = b[(o0 * nj + r0[p]) * NR * NL], v1 = b[(o0 * nj + r1[p]) * NR * NL];
+        float2 v = make_float2(v0.x + a[p] * (v1.x - v0.x), v0.y + a[p] * (v1.y - v0.y));
+        if (o1 != o0) {
+          const float2 u0 = b[(o1 * nj + r0[p]) * NR * NL], u1 = b[(o1 * nj + r1[p]) * NR * NL];
+          const float2 vv = make_float2(u0.x + a[p] * (u1.x - u0.x), u0.y + a[p] * (u1.y - u0.y));
+          v = make_float2(v.x + w * (vv.x - v.x), v.y + w * (vv.y - v.y));
+        }
+        hr[p] = v;
+      }
+      const float2 y = yrow[r];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const float2 m = cmulc(hr[i], y);
+        z[i].x += m.x;
+        z[i].y += m.y;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+          const float2 gg = cmulc(hr[i], hr[j]);
+          G[tri(i, j)].x += gg.x;
+          G[tri(i, j)].y += gg.y;
+        }
+      }
+    }
+    float gd[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      G[tri(i, i)].x += s2;
+      gd[i] = G[tri(i, i)].x;
+    }
+    bool ok = true;
+    float linv[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {  // Cholesky G = L L^H in place
+      float dj = G[tri(j, j)].x;
+#pragma unroll
+      for (int kk = 0; kk < j; ++kk) dj -= G[tri(j, kk)].x * G[tri(j, kk)].x + G[tri(j, kk)].y * G[tri(j, kk)].y;
+      ok = ok && (dj > kPivotRel * gd[j]);
+      const float ljj = sqrtf(fmaxf(dj, FLT_MIN));
+      const float inv = 1.f / ljj;
+      G[tri(j, j)] = make_float2(ljj, 0.f);
+      linv[j] = inv;
+#pragma unroll
+      for (int i = j + 1; i < NL; ++i) {
+        float2 acc = G[tri(i, j)];
+#pragma unroll
+        for (int kk = 0; kk < j; ++kk) {
+          const float2 m = cmulc(G[tri(j, kk)], G[tri(i, kk)]);
+          acc.x -= m.x;
+          acc.y -= m.y;
+        }
+        G[tri(i, j)] = make_float2(acc.x * inv, acc.y * inv);
+      }
+    }
+    float2 wv[NL], xh[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {  // L w = z
+      float2 acc = z[i];
+#pragma unroll
+      for (int kk = 0; kk < i; ++kk) {
+        const float2 m = cmul(G[tri(i, kk)], wv[kk]);
+        acc.x -= m.x;
+        acc.y -= m.y;
+      }
+      wv[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+    }
+#pragma unroll
+    for (int i = NL - 1; i >= 0; --i) {  // L^H x = w
+      float2 acc = wv[i];
+#pragma unroll
+      for (int kk = i + 1; kk < NL; ++kk) {
+        const float2 m = cmulc(G[tri(kk, i)], xh[kk]);
+        acc.x -= m.x;
+        acc.y -= m.y;
+      }
+      xh[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+    }
+    float* __restrict__ dst = u.llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2, unbias, demap
+      float2 uu[NL];
+      uu[l] = make_float2(linv[l], 0.f);
+      float acc2 = linv[l] * linv[l];
+#pragma unroll
+      for (int i = l + 1; i < NL; ++i) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int kk = l; kk < i; ++kk) {
+          const float2 m = cmul(G[tri(i, kk)], uu[kk]);
+          acc.x -= m.x;
+          acc.y -= m.y;
+        }
+        uu[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+        acc2 += uu[i].x * uu[i].x + uu[i].y * uu[i].y;
+      }
+      const float sd = s2 * acc2;
+      const float im = 1.f / (1.f - sd);
+      const float2 xo = ok ? make_float2(xh[l].x * im, xh[l].y * im)
+                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+      const float vo = ok ? sd * im : __builtin_inff();
+      switch (g.qm) {  // uniform over the item
+        case 2: demap_store<2>(dst + l * 2, xo, vo); break;
+        case 4: demap_store<4>(dst + l * 4, xo, vo); break;
+        case 6: demap_store<6>(dst + l * 6, xo, vo); break;
+        default: demap_store<8>(dst + l * 8, xo, vo); break;
+      }
+    }
+  }
+}
+
+__global__ void batch_reset_kernel(BatchHdr* __restrict__ hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->head = 0u;
+}
+
+__global__ void __launch_bounds__(256) batch_kernel(char* __restrict__ plan) {
+  __shared__ float2 lds[kBatchLds];
+  __shared__ int s_item;
+  BatchHdr* hdr = reinterpret_cast<BatchHdr*>(plan);
+  const BatchUe* ues = reinterpret_cast<const BatchUe*>(plan + kBatchUeOff);
+  const int n_items = hdr->n_items;
+  const BatchItem* items = reinterpret_cast<const BatchItem*>(plan + hdr->items_off);
+  for (;;) {
+    if (threadIdx.x == 0) s_item = (int)atomicAdd(&hdr->head, 1u);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // every thread has read s_item before it is overwritten
+    if (it >= n_items) break;  // uniform over the block: every wave leaves the loop here
+    const BatchItem item = items[it];
+    const BatchUe& u = ues[item.ue];
+    const Geom& g = u.g;  // read in place (a private copy indexed at run time would spill)
+    const int C = g.comb, T = g.td, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot;
+    // pilot range of the tile: a port's pilot indices do not decrease with the subcarrier
+    int jlo = J, jhi = 0;
+    for (int p = 0; p < NL; ++p) {
+      int j0, j1;
+      float a;
+      freq_rule(g, p, item.k0, j0, j1, a);
+      jlo = min(jlo, j0);
+      freq_rule(g, p, item.k0 + item.nk - 1, j0, j1, a);
+      jhi = max(jhi, j1);
+    }
+    const int nj = jhi - jlo + 1;
+    // 1. LS estimate at those pilots, every occasion: lds[o][j - jlo][r][p]
+    const int n_ls = g.n_occ * nj * NR * NL;
+    const float inv_t = 1.f / (float)T;
+    for (int f = threadIdx.x; f < n_ls; f += blockDim.x) {
+      const int p = f % NL;
+      const int r = (f / NL) % NR;
+      const int jj = (f / (NL * NR)) % nj;
+      const int o = f / (NL * NR * nj);
+      const int j = jlo + jj;
+      const int k = C * j + (p & (C - 1));
+      float2 acc = make_float2(0.f, 0.f);
+      if (k < g.n_sc) {
+        for (int t = 0; t < T; ++t) {
+          const float2 y = u.rx[((int64_t)(g.sym0[o] + t) * g.n_sc + k) * NR + r];
+          const float2 q = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
+          const float2 m = cmulc(q, y);  // y conj(q)
+          acc.x += m.x;
+          acc.y += m.y;
+        }
+      }
+      lds[f] = make_float2(acc.x * inv_t, acc.y * inv_t);
+    }
+    __syncthreads();
+    // 2. the tile's resource elements
+    switch (NL) {
+      case 1: detect_tile<1>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      case 2: detect_tile<2>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      case 3: detect_tile<3>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      case 4: detect_tile<4>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      case 5: detect_tile<5>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      case 6: detect_tile<6>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      case 7: detect_tile<7>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+      default: detect_tile<8>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+    }
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+}  // namespace
+
+// Pilot rows a tile of nk subcarriers starting at k0 needs (exact, by the interpolation rule).
+int batch_tile_rows(const Geom& g, int k0, int nk) {
+  int jlo = g.n_pilot, jhi = 0;
+  for (int p = 0; p < g.n_layers; ++p) {
+    const int c = p & (g.comb - 1);
+    const int jp = (g.n_sc - c + g.comb - 1) / g.comb;
+    const int last = c + g.comb * (jp - 1);
+    auto rule = [&](int k, int& j0, int& j1) {
+      if (k <= c) j0 = j1 = 0;
+      else if (k >= last) j0 = j1 = jp - 1;
+      else { j0 = (k - c) / g.comb; j1 = j0 + 1; }
+    };
+    int j0, j1;
+    rule(k0, j0, j1);
+    jlo = j0 < jlo ? j0 : jlo;
+    rule(k0 + nk - 1, j0, j1);
+    jhi = j1 > jhi ? j1 : jhi;
+  }
+  return g.n_occ * (jhi - jlo + 1);
+}
+
+hipError_t launch_batch(void* plan, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<BatchHdr*>(plan));
+  hipLaunchKernelGGL(batch_kernel, dim3(blocks), dim3(256), 0, s, static_cast<char*>(plan));
+  return hipGetLastError();
+}
+
+}  // namespace ranphy

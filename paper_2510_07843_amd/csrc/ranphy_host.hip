@@ -5,6 +5,11 @@
 // calls.
 #include <stdint.h>
 
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "batch.h"
 #include "geom.h"
 #include "ranphy.h"
 
@@ -303,6 +308,84 @@ int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const flo
     if (e != hipSuccess) return RANPHY_ERR_LAUNCH;
   }
   return RANPHY_OK;
+}
+
+// ---- many UEs in one persistent launch ----------------------------------------------------
+
+static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<char>* out) {
+  if (ues == nullptr || n_ue < 1 || tile_re < 1) return RANPHY_ERR_INVALID;
+  std::vector<ranphy::BatchUe> recs(n_ue);
+  std::vector<ranphy::BatchItem> items;
+  for (int u = 0; u < n_ue; ++u) {
+    const ranphy_ue& e = ues[u];
+    if (e.desc.n_slots != 1) return RANPHY_ERR_INVALID;
+    Geom g;
+    const int rc = ranphy::make_geom(&e.desc, &g);
+    if (rc) return rc;
+    if (g.n_layers > ranphy::kBatchMaxLayers) return RANPHY_ERR_UNSUPPORTED;
+    if (!ranphy::aligned8(e.rx) || !ranphy::aligned8(e.pilots) || !ranphy::aligned8(e.llr) ||
+        e.noise_var == nullptr || ((uintptr_t)e.noise_var & 3u))
+      return RANPHY_ERR_INVALID;
+    recs[u].g = g;
+    recs[u].rx = reinterpret_cast<const float2*>(e.rx);
+    recs[u].pil = reinterpret_cast<const float2*>(e.pilots);
+    recs[u].nv = e.noise_var;
+    recs[u].llr = e.llr;
+    // tiles of about tile_re resource elements whose pilot estimates fit the block's LDS
+    const int per = g.n_rx * g.n_layers;
+    const int want = std::max(1, tile_re / g.n_dsym);
+    for (int k0 = 0; k0 < g.n_sc;) {
+      int nk = std::min(want, g.n_sc - k0);
+      while (nk > 1 && ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) nk = (nk + 1) / 2;
+      if (ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) return RANPHY_ERR_UNSUPPORTED;
+      // class: layers, modulation, antennas
+      items.push_back({u, k0, nk, (g.n_layers * 16 + g.qm) * 128 + g.n_rx});
+      k0 += nk;
+    }
+  }
+  // heaviest classes first (Gram work per RE ~ Nr Nl (Nl + 1) / 2), one class's items adjacent
+  auto cost = [&](const ranphy::BatchItem& it) {
+    const Geom& g = recs[it.ue].g;
+    return (int64_t)g.n_rx * g.n_layers * (g.n_layers + 1) / 2;
+  };
+  std::stable_sort(items.begin(), items.end(), [&](const ranphy::BatchItem& a,
+                                                   const ranphy::BatchItem& b) {
+    const int64_t ca = cost(a), cb = cost(b);
+    if (ca != cb) return ca > cb;
+    return a.cls < b.cls;
+  });
+  ranphy::BatchHdr hdr{};
+  hdr.head = 0;
+  hdr.n_items = (int)items.size();
+  hdr.n_ue = n_ue;
+  const int64_t ue_bytes = (int64_t)sizeof(ranphy::BatchUe) * n_ue;
+  hdr.items_off = (int)((ranphy::kBatchUeOff + ue_bytes + 255) & ~int64_t(255));
+  out->assign((size_t)hdr.items_off + sizeof(ranphy::BatchItem) * items.size(), 0);
+  std::memcpy(out->data(), &hdr, sizeof(hdr));
+  std::memcpy(out->data() + ranphy::kBatchUeOff, recs.data(), (size_t)ue_bytes);
+  std::memcpy(out->data() + hdr.items_off, items.data(), sizeof(ranphy::BatchItem) * items.size());
+  return RANPHY_OK;
+}
+
+int64_t ranphy_batch_plan_bytes(const ranphy_ue* ues, int n_ue, int tile_re) {
+  std::vector<char> buf;
+  const int rc = batch_build(ues, n_ue, tile_re, &buf);
+  return rc ? rc : (int64_t)buf.size();
+}
+
+int ranphy_batch_plan(const ranphy_ue* ues, int n_ue, int tile_re, void* plan,
+                      int64_t plan_bytes) {
+  std::vector<char> buf;
+  const int rc = batch_build(ues, n_ue, tile_re, &buf);
+  if (rc) return rc;
+  if (plan == nullptr || ((uintptr_t)plan & 255u) || plan_bytes < (int64_t)buf.size())
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(hipMemcpy(plan, buf.data(), buf.size(), hipMemcpyHostToDevice));
+}
+
+int ranphy_batch_run(void* plan, int n_blocks, void* stream) {
+  if (plan == nullptr || ((uintptr_t)plan & 255u) || n_blocks < 1) return RANPHY_ERR_INVALID;
+  return ranphy::status_of(ranphy::launch_batch(plan, n_blocks, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

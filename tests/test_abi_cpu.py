@@ -174,3 +174,34 @@ def test_fused_detect_demap_validation(L):
     assert L.ranphy_mmse_llr(ctypes.byref(d2), a, a, 0, a, None, None, a, 0, None) == -2
     d3 = _desc(n_rx=16, n_layers=4)
     assert L.ranphy_mmse_llr(ctypes.byref(d3), a, a, 0, a, a, a, a, 1, None) == -2
+
+
+def test_batch_plan_validation(L):
+    P = ctypes.c_void_p
+
+    def ue(**kw):
+        u = ranphy.UeRec()
+        a = dict(GOOD, n_slots=1)
+        a.update(kw)
+        u.desc = ranphy.SlotDesc.make(**a)
+        u.rx = u.pilots = u.noise_var = u.llr = 0x1000
+        return u
+
+    arr = (ranphy.UeRec * 2)(ue(), ue(qm=6))
+    n = L.ranphy_batch_plan_bytes(arr, 2, 256)
+    assert n > 256
+    # a plan smaller than needed, or misaligned, is refused before any copy
+    assert L.ranphy_batch_plan(arr, 2, 256, P(0x10000), n - 1) == -1
+    assert L.ranphy_batch_plan(arr, 2, 256, P(0x10010), n) == -1
+    assert L.ranphy_batch_plan_bytes(arr, 0, 256) == -1
+    assert L.ranphy_batch_plan_bytes(arr, 2, 0) == -1
+    bad = (ranphy.UeRec * 1)(ue(n_slots=2))
+    assert L.ranphy_batch_plan_bytes(bad, 1, 256) == -1
+    bad = (ranphy.UeRec * 1)(ue(n_rx=16, n_layers=9, dmrs_comb=8, dmrs_td=2))
+    assert L.ranphy_batch_plan_bytes(bad, 1, 256) == -2  # more than 8 layers
+    u = ue()
+    u.rx = 0x1004
+    bad = (ranphy.UeRec * 1)(u)
+    assert L.ranphy_batch_plan_bytes(bad, 1, 256) == -1
+    assert L.ranphy_batch_run(None, 4, None) == -1
+    assert L.ranphy_batch_run(P(0x10000), 0, None) == -1
