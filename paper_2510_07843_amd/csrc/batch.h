@@ -26,7 +26,11 @@ struct BatchHdr {
   int items_off;
 };
 
-constexpr int kBatchLds = 6144;  // complex values of staged pilot estimates per block (48 KB)
+constexpr int kBatchLds = 4096;  // complex values of staged pilot estimates per block (32 KB)
+// One DMRS occasion: the channel is held over the slot, so each subcarrier's Gram factor is
+// formed once per tile and staged in LDS for the tile's resource elements.
+constexpr int kBatchFactSc = 56;  // subcarriers per tile of a one-occasion UE
+constexpr int kBatchFactNP = 36;  // lower-triangle entries of an 8 x 8 factor
 constexpr int kBatchUeOff = 256;
 constexpr int kBatchMaxLayers = 8;
 

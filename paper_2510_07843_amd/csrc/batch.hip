@@ -13,10 +13,15 @@
 // graph).  An item is processed by one block without depending on any other:
 //   1. the LS estimate (Sec. III-B: channel estimation) of every pilot the tile's
 //      subcarriers interpolate from, per occasion, into LDS;
-//   2. per resource element of the tile (all data symbols): frequency and time
-//      interpolation from LDS, Gram and matched filter streamed over the receive antennas,
-//      Cholesky factorisation and forward / backward substitution (Sec. IV, Fig. 4),
-//      unbiasing, and the max-log LLRs written to the UE's output.
+//   2. with one DMRS occasion (the channel held over the slot): each subcarrier's Gram
+//      G = H^H H + s2 I, one (subcarrier, entry) per thread, then its Cholesky factor
+//      (Sec. IV, Fig. 4), reciprocal diagonal and d = diag(G^-1), one subcarrier per
+//      thread, staged in LDS; per resource element (all data symbols) the matched filter
+//      streamed over the receive antennas, forward / backward substitution with the staged
+//      factor, unbiasing, and the max-log LLRs written to the UE's output;
+//   2'. with several occasions (a time-varying estimate): per resource element the
+//      interpolation in frequency and time, Gram and matched filter, factorisation,
+//      substitution, unbiasing and LLRs.
 // Layers 1..8 (a template parameter: one branch per item, uniform over the block),
 // antennas 1..64, every modulation and DMRS configuration of the library.
 #include <float.h>
@@ -183,12 +188,208 @@ __device__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk, int
   }
 }
 
+// Channel value of port p at antenna r for the subcarrier whose interpolation rows and
+// weight are (r0, r1, a), one occasion: rows[j][r][p].
+__device__ __forceinline__ float2 row_interp(const float2* __restrict__ rows, int NR, int NL,
+                                             int r0, int r1, float a, int r, int p) {
+  const float2 v0 = rows[(r0 * NR + r) * NL + p], v1 = rows[(r1 * NR + r) * NL + p];
+  return make_float2(v0.x + a * (v1.x - v0.x), v0.y + a * (v1.y - v0.y));
+}
+
+// One occasion: Gram, Cholesky factor, reciprocal diagonal and d = diag(G^-1) of each of the
+// tile's subcarriers into LDS.  fac[kk][tri(i, j)] holds L, aux[kk][0..NL) 1 / L_ii,
+// aux[kk][NL..2NL) d, aux[kk][2NL] 1 where the factorisation succeeded, else 0.
+template <int NL>
+__device__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
+                            const float2* __restrict__ rows, float2* __restrict__ fac,
+                            float* __restrict__ aux) {
+  constexpr int NP = NL * (NL + 1) / 2;
+  const int NR = g.n_rx;
+  for (int f = threadIdx.x; f < nk * NP; f += blockDim.x) {
+    const int kk = f / NP;
+    const int e = f - kk * NP;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int j = e - i * (i + 1) / 2;
+    const int k = k0 + kk;
+    int ri0, ri1, rj0, rj1;
+    float ai, aj;
+    freq_rule(g, i, k, ri0, ri1, ai);
+    freq_rule(g, j, k, rj0, rj1, aj);
+    ri0 -= jlo; ri1 -= jlo; rj0 -= jlo; rj1 -= jlo;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int r = 0; r < NR; ++r) {  // the order of the per-RE path's sums
+      const float2 hi = row_interp(rows, NR, NL, ri0, ri1, ai, r, i);
+      const float2 hj = row_interp(rows, NR, NL, rj0, rj1, aj, r, j);
+      const float2 gg = cmulc(hi, hj);
+      acc.x += gg.x;
+      acc.y += gg.y;
+    }
+    fac[kk * kBatchFactNP + e] = acc;
+  }
+  __syncthreads();
+  const float s2 = *u.nv;
+  for (int kk = threadIdx.x; kk < nk; kk += blockDim.x) {
+    float2 G[NP];
+#pragma unroll
+    for (int e = 0; e < NP; ++e) G[e] = fac[kk * kBatchFactNP + e];
+    float gd[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+      G[tri(i, i)].x += s2;
+      gd[i] = G[tri(i, i)].x;
+    }
+    bool ok = true;
+    float linv[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      float dj = G[tri(j, j)].x;
+#pragma unroll
+      for (int kq = 0; kq < j; ++kq) dj -= G[tri(j, kq)].x * G[tri(j, kq)].x + G[tri(j, kq)].y * G[tri(j, kq)].y;
+      ok = ok && (dj > kPivotRel * gd[j]);
+      const float ljj = sqrtf(fmaxf(dj, FLT_MIN));
+      const float inv = 1.f / ljj;
+      G[tri(j, j)] = make_float2(ljj, 0.f);
+      linv[j] = inv;
+#pragma unroll
+      for (int i = j + 1; i < NL; ++i) {
+        float2 acc = G[tri(i, j)];
+#pragma unroll
+        for (int kq = 0; kq < j; ++kq) {
+          const float2 m = cmulc(G[tri(j, kq)], G[tri(i, kq)]);
+          acc.x -= m.x;
+          acc.y -= m.y;
+        }
+        G[tri(i, j)] = make_float2(acc.x * inv, acc.y * inv);
+      }
+    }
+    float* ax = aux + kk * (2 * kBatchMaxLayers + 1);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2
+      float2 uu[NL];
+      uu[l] = make_float2(linv[l], 0.f);
+      float acc2 = linv[l] * linv[l];
+#pragma unroll
+      for (int i = l + 1; i < NL; ++i) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int kq = l; kq < i; ++kq) {
+          const float2 m = cmul(G[tri(i, kq)], uu[kq]);
+          acc.x -= m.x;
+          acc.y -= m.y;
+        }
+        uu[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+        acc2 += uu[i].x * uu[i].x + uu[i].y * uu[i].y;
+      }
+      ax[l] = linv[l];
+      ax[NL + l] = acc2;
+    }
+    ax[2 * NL] = ok ? 1.f : 0.f;
+#pragma unroll
+    for (int e = 0; e < NP; ++e) fac[kk * kBatchFactNP + e] = G[e];
+  }
+  __syncthreads();
+}
+
+// One occasion, per resource element with the staged factor: matched filter, substitutions,
+// unbiasing, LLRs.
+template <int NL>
+__device__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
+                                 const float2* __restrict__ rows,
+                                 const float2* __restrict__ fac, const float* __restrict__ aux) {
+  constexpr int NP = NL * (NL + 1) / 2;
+  const int NR = g.n_rx, ND = g.n_dsym;
+  const float s2 = *u.nv;
+  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
+    const int d = e / nk;
+    const int kk = e - d * nk;
+    const int k = k0 + kk;
+    int r0[NL], r1[NL];
+    float a[NL];
+#pragma unroll
+    for (int p = 0; p < NL; ++p) {
+      int j0, j1;
+      freq_rule(g, p, k, j0, j1, a[p]);
+      r0[p] = j0 - jlo;
+      r1[p] = j1 - jlo;
+    }
+    float2 z[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
+    const float2* __restrict__ yrow = u.rx + ((int64_t)g.dsym[d] * g.n_sc + k) * NR;
+    for (int r = 0; r < NR; ++r) {
+      const float2 y = yrow[r];
+#pragma unroll
+      for (int i = 0; i < NL; ++i) {
+        const float2 m = cmulc(row_interp(rows, NR, NL, r0[i], r1[i], a[i], r, i), y);
+        z[i].x += m.x;
+        z[i].y += m.y;
+      }
+    }
+    const float2* L = fac + kk * kBatchFactNP;
+    const float* ax = aux + kk * (2 * kBatchMaxLayers + 1);
+    const bool ok = ax[2 * NL] != 0.f;
+    float2 wv[NL], xh[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {  // L w = z
+      float2 acc = z[i];
+#pragma unroll
+      for (int kq = 0; kq < i; ++kq) {
+        const float2 m = cmul(L[tri(i, kq)], wv[kq]);
+        acc.x -= m.x;
+        acc.y -= m.y;
+      }
+      wv[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
+    }
+#pragma unroll
+    for (int i = NL - 1; i >= 0; --i) {  // L^H x = w
+      float2 acc = wv[i];
+#pragma unroll
+      for (int kq = i + 1; kq < NL; ++kq) {
+        const float2 m = cmulc(L[tri(kq, i)], xh[kq]);
+        acc.x -= m.x;
+        acc.y -= m.y;
+      }
+      xh[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
+    }
+    float* __restrict__ dst = u.llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const float sd = s2 * ax[NL + l];
+      const float im = 1.f / (1.f - sd);
+      const float2 xo = ok ? make_float2(xh[l].x * im, xh[l].y * im)
+                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+      const float vo = ok ? sd * im : __builtin_inff();
+      switch (g.qm) {
+        case 2: demap_store<2>(dst + l * 2, xo, vo); break;
+        case 4: demap_store<4>(dst + l * 4, xo, vo); break;
+        case 6: demap_store<6>(dst + l * 6, xo, vo); break;
+        default: demap_store<8>(dst + l * 8, xo, vo); break;
+      }
+    }
+  }
+}
+
+template <int NL>
+__device__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+                             const float2* rows, float2* fac, float* aux) {
+  if (g.n_occ == 1) {
+    factor_tile<NL>(u, g, k0, nk, jlo, rows, fac, aux);
+    detect_tile_fact<NL>(u, g, k0, nk, jlo, rows, fac, aux);
+  } else {
+    detect_tile<NL>(u, g, k0, nk, jlo, nj, rows);
+  }
+}
+
 __global__ void batch_reset_kernel(BatchHdr* __restrict__ hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) hdr->head = 0u;
 }
 
-__global__ void __launch_bounds__(256) batch_kernel(char* __restrict__ plan) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) batch_kernel(
+    char* __restrict__ plan) {
   __shared__ float2 lds[kBatchLds];
+  __shared__ float2 fac[kBatchFactSc * kBatchFactNP];
+  __shared__ float aux[kBatchFactSc * (2 * kBatchMaxLayers + 1)];
   __shared__ int s_item;
   BatchHdr* hdr = reinterpret_cast<BatchHdr*>(plan);
   const BatchUe* ues = reinterpret_cast<const BatchUe*>(plan + kBatchUeOff);
@@ -239,15 +440,15 @@ __global__ void __launch_bounds__(256) batch_kernel(char* __restrict__ plan) {
     }
     __syncthreads();
     // 2. the tile's resource elements
-    switch (NL) {
-      case 1: detect_tile<1>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      case 2: detect_tile<2>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      case 3: detect_tile<3>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      case 4: detect_tile<4>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      case 5: detect_tile<5>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      case 6: detect_tile<6>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      case 7: detect_tile<7>(u, g, item.k0, item.nk, jlo, nj, lds); break;
-      default: detect_tile<8>(u, g, item.k0, item.nk, jlo, nj, lds); break;
+    switch (NL) {  // uniform over the block
+      case 1: process_tile<1>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      case 2: process_tile<2>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      case 3: process_tile<3>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      case 4: process_tile<4>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      case 5: process_tile<5>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      case 6: process_tile<6>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      case 7: process_tile<7>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
+      default: process_tile<8>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
     }
     __syncthreads();  // LDS is reused by the next item
   }

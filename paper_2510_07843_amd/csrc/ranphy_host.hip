@@ -333,7 +333,8 @@ static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<
     recs[u].llr = e.llr;
     // tiles of about tile_re resource elements whose pilot estimates fit the block's LDS
     const int per = g.n_rx * g.n_layers;
-    const int want = std::max(1, tile_re / g.n_dsym);
+    int want = std::max(1, tile_re / g.n_dsym);
+    if (g.n_occ == 1) want = std::min(want, ranphy::kBatchFactSc);
     for (int k0 = 0; k0 < g.n_sc;) {
       int nk = std::min(want, g.n_sc - k0);
       while (nk > 1 && ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) nk = (nk + 1) / 2;
