@@ -2,8 +2,9 @@
 
 A step is one pass of the whole path -- channel estimation, detection, demapping -- over one
 batch of synthetic slots already resident in HBM: chest_ls -> mmse_llr (detection with the
-demapping in its epilogue) where the shape takes the matrix-core detector, else chest_ls ->
-mmse_detect -> llr_demap; the three-call chain is timed beside the fused one.  The default workload is 64 Rx x 16
+demapping in its epilogue) where the shape takes the matrix-core detector; for up to 8 layers
+otherwise the whole chain as one launch (receive), with the three-call chain chest_ls ->
+mmse_detect -> llr_demap timed beside it.  The default workload is 64 Rx x 16
 layers, 273 PRB (3276 subcarriers) x 14 symbols, 64QAM, one double-symbol DMRS occasion
 (comb 8, time cover 2), exponential-PDP TDL channel with 300 ns rms delay spread, SNR 0..30
 dB in 5 dB steps, 20 slots per SNR point: 140 slots, 39312 data REs each.
@@ -86,7 +87,12 @@ def algorithmic_costs(shape, h_res=0):
     llr = dict(bytes=re * NL * (8 + 4) + re * NL * Q * 4, flops=re * NL * Q * 6)
     fused = dict(bytes=mmse["bytes"] - re * NL * (8 + 4) + re * NL * Q * 4,
                  flops=mmse["flops"] + llr["flops"])
-    return dict(chest_ls=chest, mmse_detect=mmse, llr_demap=llr, mmse_llr=fused, data_re=re)
+    # one launch: the whole received grid, the pilots and the noise variances in, LLRs out
+    receive = dict(bytes=S * shape.n_symb * nsc * NR * 8 + S * occ * T * J * NL * 8 + S * 4
+                   + re * NL * Q * 4,
+                   flops=chest["flops"] + mmse["flops"] + llr["flops"])
+    return dict(chest_ls=chest, mmse_detect=mmse, llr_demap=llr, mmse_llr=fused,
+                receive=receive, data_re=re)
 
 
 def fused_eligible(shape) -> bool:
@@ -151,7 +157,7 @@ def detection_quality(torch, ranphy, synth):
     return out
 
 
-def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, fused, scs_hz, reps=200):
+def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, path, scs_hz, reps=200):
     """One slot through the whole chain: mean time per slot launched eagerly (one call per
     step, synchronised at the end) and replayed from a HIP graph holding the slot's launches;
     the replayed LLRs must equal the eager ones bit for bit."""
@@ -166,8 +172,11 @@ def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, fused, scs_hz
     l1 = torch.empty(ranphy.buffer_floats(one, ranphy.BUF_LLR), dtype=torch.float32, device=dev)
 
     def chain():
+        if path == "receive":
+            ranphy.receive(one, rx1, pil1, nv1, llr=l1)
+            return
         ranphy.chest_ls(one, rx1, pil1, h=h1, h_res=h_res)
-        if fused:
+        if path == "fused":
             ranphy.mmse_llr(one, rx1, h1, nv1, h_res=h_res, llr=l1, precision=prec)
         else:
             ranphy.mmse_detect(one, rx1, h1, nv1, h_res=h_res, x=x1, nv=v1, precision=prec)
@@ -429,8 +438,9 @@ def main():
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="input precision of the detector's Gram and matched filter")
-    ap.add_argument("--path", default="auto", choices=["auto", "fused", "separate"],
-                    help="fused detection + demapping (matrix-core shapes) or three calls")
+    ap.add_argument("--path", default="auto", choices=["auto", "fused", "receive", "separate"],
+                    help="fused detection + demapping (matrix-core shapes), the whole chain "
+                         "in one launch (up to 8 layers) or three calls")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true",
@@ -485,12 +495,23 @@ def main():
     llr = torch.empty(ranphy.buffer_floats(shape, ranphy.BUF_LLR), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
-    fused = fused_eligible(shape) if args.path == "auto" else args.path == "fused"
+    if args.path != "auto":
+        path = args.path
+    elif fused_eligible(shape):
+        path = "fused"
+    elif shape.n_layers <= 8 and h_res == ranphy.H_PILOT and prec == ranphy.PREC_FP32:
+        path = "receive"
+    else:
+        path = "separate"
+    fused = path == "fused"
 
-    def run_timed(precision, fused, refine=None):
+    def run_timed(precision, fused, refine=None, one_launch=False):
         """Warm up, then time exactly args.steps steps; returns (ms per step, per-kernel ms).
-        refine = (params, min_noise_var, workspace) inserts the learned estimate refinement."""
+        refine = (params, min_noise_var, workspace) inserts the learned estimate refinement;
+        one_launch times the whole chain as one kernel."""
         names = ("chest_ls", "mmse_llr") if fused else ("chest_ls", "mmse_detect", "llr_demap")
+        if one_launch:
+            names = ("receive",)
         if refine is not None:
             names = names[:1] + ("cnn_denoise",) + names[1:]
         ev = {n: [] for n in names}
@@ -501,6 +522,12 @@ def main():
             base = 2 if refine is not None else 1  # mark index after the steps before detection
             if record:
                 marks[0].record()
+            if one_launch:
+                ranphy.receive(shape, rx, pil, nvar, llr=llr)
+                if record:
+                    marks[1].record()
+                    ev["receive"].append((marks[0], marks[1]))
+                return
             ranphy.chest_ls(shape, rx, pil, h=h, h_res=h_res)
             if record:
                 marks[1].record()
@@ -535,7 +562,7 @@ def main():
         return (t_start.elapsed_time(t_end) / args.steps,
                 {n: float(np.mean([a.elapsed_time(c) for a, c in ev[n]])) for n in names})
 
-    ms_step, kern_ms = run_timed(prec, fused)
+    ms_step, kern_ms = run_timed(prec, fused, one_launch=path == "receive")
     names = tuple(kern_ms)
 
     costs = algorithmic_costs(shape, h_res)
@@ -545,7 +572,7 @@ def main():
     # Dominant kernel and its bound: time at the HBM roof vs at the compute roof.
     dom = max(names, key=lambda n: kern_ms[n])
     c = costs[dom]
-    on_mfma = dom in ("mmse_detect", "mmse_llr")
+    on_mfma = dom in ("mmse_detect", "mmse_llr") and fused_eligible(shape)
     compute_peak = FP32_MFMA_PEAK_TFLOPS if on_mfma else FP32_VALU_PEAK_TFLOPS
     t_bytes = c["bytes"] / (HBM_PEAK_GBS * 1e9)
     t_flops = c["flops"] / (compute_peak * 1e12)
@@ -574,7 +601,7 @@ def main():
                                f"{shape.n_slots} slots, h_res={args.h_res}, detector {args.prec}",
                    "slots": shape.n_slots, "data_re_per_step": re,
                    "path": ("plain_fp32" if args.prec == "fp32" else f"mixed_{args.prec}")
-                           + ("_fused" if fused else "_separate")},
+                           + "_" + path},
         "kernels_ms": kern_ms,
         "roofline": roof,
     }
@@ -586,7 +613,11 @@ def main():
             "bytes_per_launch": cc["bytes"], "flops_per_launch": cc["flops"]}
     if not args.no_latency:
         out["slot_latency"] = slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec,
-                                           fused, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])
+                                           path, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])
+    if path == "receive":  # the three-call chain on the same batch, for comparison
+        v_ms, v_k = run_timed(prec, False)
+        out["variants"] = {"separate": {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
+                                        "kernels_ms": v_k}}
     if args.workload == "m" and h_res == ranphy.H_PILOT and not args.no_variants:
         variants = {}
         quality = detection_quality(torch, ranphy, synth)

@@ -237,6 +237,20 @@ RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params
                                   const float* h_in, float* h_out, void* workspace,
                                   int64_t workspace_bytes, void* stream);
 
+/*
+ * The whole chain in one launch for up to 8 layers: LS estimation at the pilots (abstract,
+ * Sec. III-B), interpolation, LMMSE detection by Cholesky factorisation and substitution
+ * (Sec. IV, Fig. 4), unbiasing and max-log demapping, computed tile by tile with the pilot
+ * estimates of each tile of subcarriers held on chip, so only the received grid, the pilots
+ * and the LLRs travel through device memory.  Same results as ranphy_chest_ls (pilot
+ * resolution) -> ranphy_mmse_detect -> ranphy_llr_demap up to rounding order.
+ *   rx, pilots, noise_var as for ranphy_chest_ls / ranphy_mmse_detect;
+ *   llr out [slot][dsym][sc][layer][qm] float.
+ * More than 8 layers: RANPHY_ERR_UNSUPPORTED (use the three calls or ranphy_mmse_llr).
+ */
+RANPHY_API int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilots,
+                              const float* noise_var, float* llr, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Many UEs of uneven allocations in one persistent launch (the scheduling and divergence
  * costs of SIMT processing the paper weighs in Sec. V): for every UE, LS estimation at the

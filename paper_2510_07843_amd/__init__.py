@@ -35,7 +35,7 @@ EXPORTED_SYMBOLS = (
     "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_mmse_llr",
     "ranphy_llr_demap", "ranphy_cnn_param_count", "ranphy_cnn_workspace_bytes",
     "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
-    "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run",
+    "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run", "ranphy_receive",
 )
 
 
@@ -112,10 +112,11 @@ def lib() -> ctypes.CDLL:
         L.ranphy_batch_plan_bytes.restype = I64
         L.ranphy_batch_plan.argtypes = [UE, I, I, P, I64]
         L.ranphy_batch_run.argtypes = [P, I, P]
+        L.ranphy_receive.argtypes = [D, P, P, P, P, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
                   "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
                   "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_batch_plan",
-                  "ranphy_batch_run"):
+                  "ranphy_batch_run", "ranphy_receive"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -230,6 +231,22 @@ def mmse_llr(shape, rx: torch.Tensor, h: torch.Tensor, noise_var: torch.Tensor,
     pl = _as_dev(llr, "llr", torch.float32, nl)
     _check("ranphy_mmse_llr", lib().ranphy_mmse_llr(ctypes.byref(d), *args, h_res, pn, px, pv, pl,
                                                     precision, _stream(stream)))
+    return llr
+
+
+def receive(shape, rx: torch.Tensor, pilots: torch.Tensor, noise_var: torch.Tensor,
+            llr: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The whole chain (LS estimate, interpolation, detection, demapping) in one launch, up to
+    8 layers; returns the LLRs [slot][dsym][sc][layer][qm]."""
+    d = desc_of(shape)
+    nl = buffer_floats(d, BUF_LLR)
+    if llr is None:
+        llr = torch.empty(nl, dtype=torch.float32, device=rx.device)
+    _check("ranphy_receive", lib().ranphy_receive(
+        ctypes.byref(d), _as_dev(rx, "rx", torch.complex64, buffer_floats(d, BUF_RX)),
+        _as_dev(pilots, "pilots", torch.complex64, buffer_floats(d, BUF_PILOTS)),
+        _as_dev(noise_var, "noise_var", torch.float32, buffer_floats(d, BUF_NOISE_VAR)),
+        _as_dev(llr, "llr", torch.float32, nl), _stream(stream)))
     return llr
 
 

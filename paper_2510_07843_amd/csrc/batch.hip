@@ -381,6 +381,62 @@ __device__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk, in
   }
 }
 
+// The LS estimate (Sec. III-B) of every pilot the tile k0 .. k0 + nk - 1 interpolates from,
+// every occasion, into rows[o][j - jlo][r][p]; returns jlo and the pilot count nj.  Ends with
+// a barrier.
+__device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, int k0, int nk,
+                             float2* __restrict__ rows, int& jlo, int& nj) {
+  const int C = g.comb, T = g.td, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot;
+  // pilot range of the tile: a port's pilot indices do not decrease with the subcarrier
+  int lo = J, hi = 0;
+  for (int p = 0; p < NL; ++p) {
+    int j0, j1;
+    float a;
+    freq_rule(g, p, k0, j0, j1, a);
+    lo = min(lo, j0);
+    freq_rule(g, p, k0 + nk - 1, j0, j1, a);
+    hi = max(hi, j1);
+  }
+  jlo = lo;
+  nj = hi - lo + 1;
+  const int n_ls = g.n_occ * nj * NR * NL;
+  const float inv_t = 1.f / (float)T;
+  for (int f = threadIdx.x; f < n_ls; f += blockDim.x) {
+    const int p = f % NL;
+    const int r = (f / NL) % NR;
+    const int jj = (f / (NL * NR)) % nj;
+    const int o = f / (NL * NR * nj);
+    const int j = jlo + jj;
+    const int k = C * j + (p & (C - 1));
+    float2 acc = make_float2(0.f, 0.f);
+    if (k < g.n_sc) {
+      for (int t = 0; t < T; ++t) {
+        const float2 y = u.rx[((int64_t)(g.sym0[o] + t) * g.n_sc + k) * NR + r];
+        const float2 q = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
+        const float2 m = cmulc(q, y);  // y conj(q)
+        acc.x += m.x;
+        acc.y += m.y;
+      }
+    }
+    rows[f] = make_float2(acc.x * inv_t, acc.y * inv_t);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void process_any(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+                            const float2* rows, float2* fac, float* aux) {
+  switch (g.n_layers) {  // uniform over the block
+    case 1: process_tile<1>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 2: process_tile<2>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 3: process_tile<3>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 4: process_tile<4>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 5: process_tile<5>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 6: process_tile<6>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 7: process_tile<7>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    default: process_tile<8>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+  }
+}
+
 __global__ void batch_reset_kernel(BatchHdr* __restrict__ hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) hdr->head = 0u;
 }
@@ -404,57 +460,64 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     const BatchItem item = items[it];
     const BatchUe& u = ues[item.ue];
     const Geom& g = u.g;  // read in place (a private copy indexed at run time would spill)
-    const int C = g.comb, T = g.td, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot;
-    // pilot range of the tile: a port's pilot indices do not decrease with the subcarrier
-    int jlo = J, jhi = 0;
-    for (int p = 0; p < NL; ++p) {
-      int j0, j1;
-      float a;
-      freq_rule(g, p, item.k0, j0, j1, a);
-      jlo = min(jlo, j0);
-      freq_rule(g, p, item.k0 + item.nk - 1, j0, j1, a);
-      jhi = max(jhi, j1);
-    }
-    const int nj = jhi - jlo + 1;
-    // 1. LS estimate at those pilots, every occasion: lds[o][j - jlo][r][p]
-    const int n_ls = g.n_occ * nj * NR * NL;
-    const float inv_t = 1.f / (float)T;
-    for (int f = threadIdx.x; f < n_ls; f += blockDim.x) {
-      const int p = f % NL;
-      const int r = (f / NL) % NR;
-      const int jj = (f / (NL * NR)) % nj;
-      const int o = f / (NL * NR * nj);
-      const int j = jlo + jj;
-      const int k = C * j + (p & (C - 1));
-      float2 acc = make_float2(0.f, 0.f);
-      if (k < g.n_sc) {
-        for (int t = 0; t < T; ++t) {
-          const float2 y = u.rx[((int64_t)(g.sym0[o] + t) * g.n_sc + k) * NR + r];
-          const float2 q = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
-          const float2 m = cmulc(q, y);  // y conj(q)
-          acc.x += m.x;
-          acc.y += m.y;
-        }
-      }
-      lds[f] = make_float2(acc.x * inv_t, acc.y * inv_t);
-    }
-    __syncthreads();
-    // 2. the tile's resource elements
-    switch (NL) {  // uniform over the block
-      case 1: process_tile<1>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      case 2: process_tile<2>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      case 3: process_tile<3>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      case 4: process_tile<4>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      case 5: process_tile<5>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      case 6: process_tile<6>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      case 7: process_tile<7>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-      default: process_tile<8>(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux); break;
-    }
+    int jlo, nj;
+    stage_pilots(u, g, item.k0, item.nk, lds, jlo, nj);
+    process_any(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux);
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
+// The whole chain for a batch of slots of one shape (up to 8 layers) in one launch: block
+// (slot, tile of nk subcarriers) stages the tile's pilot estimates and detects and demaps its
+// resource elements, as a work item of the multi-UE launch does.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
+               const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
+  __shared__ float2 lds[kBatchLds];
+  __shared__ float2 fac[kBatchFactSc * kBatchFactNP];
+  __shared__ float aux[kBatchFactSc * (2 * kBatchMaxLayers + 1)];
+  const int ntiles = (g.n_sc + nk - 1) / nk;
+  const int slot = blockIdx.x / ntiles;
+  const int k0 = (blockIdx.x - slot * ntiles) * nk;
+  BatchUe u;
+  u.g = g;
+  u.rx = rx + (int64_t)slot * g.n_symb * g.n_sc * g.n_rx;
+  u.pil = pil + (int64_t)slot * g.n_occ * g.td * g.n_pilot * g.n_layers;
+  u.nv = nvar + slot;
+  u.llr = llr + (int64_t)slot * g.n_dsym * g.n_sc * g.n_layers * g.qm;
+  const int n = min(nk, g.n_sc - k0);
+  int jlo, nj;
+  stage_pilots(u, g, k0, n, lds, jlo, nj);
+  process_any(u, g, k0, n, jlo, nj, lds, fac, aux);
+}
+
 }  // namespace
+
+// Tile width of the one-launch chain: about tile_re resource elements, at most kBatchFactSc
+// subcarriers, and pilot rows that fit the block's LDS for every tile.
+int receive_tile(const Geom& g, int tile_re) {
+  int nk = tile_re / g.n_dsym;
+  nk = nk < 1 ? 1 : (nk > kBatchFactSc ? kBatchFactSc : nk);
+  const int per = g.n_rx * g.n_layers;
+  for (;;) {
+    int worst = 0;
+    for (int k0 = 0; k0 < g.n_sc; k0 += nk) {
+      const int n = g.n_sc - k0 < nk ? g.n_sc - k0 : nk;
+      const int r = batch_tile_rows(g, k0, n);
+      worst = r > worst ? r : worst;
+    }
+    if (worst * per <= kBatchLds || nk == 1) return worst * per <= kBatchLds ? nk : 0;
+    nk = (nk + 1) / 2;
+  }
+}
+
+hipError_t launch_receive(const Geom& g, const float2* rx, const float2* pil, const float* nvar,
+                          float* llr, int nk, hipStream_t s) {
+  const int64_t ntiles = (g.n_sc + nk - 1) / nk;
+  hipLaunchKernelGGL(receive_kernel, dim3((unsigned)(g.n_slots * ntiles)), dim3(256), 0, s, g,
+                     rx, pil, nvar, llr, nk);
+  return hipGetLastError();
+}
 
 // Pilot rows a tile of nk subcarriers starting at k0 needs (exact, by the interpolation rule).
 int batch_tile_rows(const Geom& g, int k0, int nk) {

@@ -310,6 +310,25 @@ int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const flo
   return RANPHY_OK;
 }
 
+// ---- the whole chain in one launch (up to 8 layers) ----------------------------------------
+
+int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilots,
+                   const float* noise_var, float* llr, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (g.n_layers > ranphy::kBatchMaxLayers) return RANPHY_ERR_UNSUPPORTED;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (!ranphy::aligned8(rx) || !ranphy::aligned8(pilots) || !ranphy::aligned8(llr) ||
+      noise_var == nullptr || ((uintptr_t)noise_var & 3u))
+    return RANPHY_ERR_INVALID;
+  const int nk = ranphy::receive_tile(g, 256);
+  if (nk < 1) return RANPHY_ERR_UNSUPPORTED;
+  return ranphy::status_of(ranphy::launch_receive(
+      g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(pilots), noise_var,
+      llr, nk, static_cast<hipStream_t>(stream)));
+}
+
 // ---- many UEs in one persistent launch ----------------------------------------------------
 
 static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<char>* out) {

@@ -96,6 +96,7 @@ def _calls(L, d, p):
         L.ranphy_mmse_detect(ctypes.byref(d), P(p), P(p), 0, P(p), P(p), P(p), None),
         L.ranphy_llr_demap(ctypes.byref(d), P(p), P(p), P(p), None),
         L.ranphy_mmse_llr(ctypes.byref(d), P(p), P(p), 0, P(p), P(p), P(p), P(p), 0, None),
+        L.ranphy_receive(ctypes.byref(d), P(p), P(p), P(p), P(p), None),
     ]
 
 
@@ -103,7 +104,7 @@ def _calls(L, d, p):
 def test_invalid_descriptors_rejected_before_launch(L, kw, code):
     d = _desc(**kw)
     # Pointers that would fault if touched; validation must stop first.
-    assert _calls(L, d, 0x1000) == [code] * 4
+    assert _calls(L, d, 0x1000) == [code] * 5
     assert L.ranphy_buffer_floats(ctypes.byref(d), ranphy.BUF_RX, 0) == code
 
 
@@ -112,12 +113,19 @@ def test_null_descriptor(L):
     assert L.ranphy_chest_ls(None, P(0x1000), P(0x1000), P(0x1000), 0, None) == -1
     assert L.ranphy_mmse_detect(None, P(8), P(8), 0, P(8), P(8), P(8), None) == -1
     assert L.ranphy_llr_demap(None, P(8), P(8), P(8), None) == -1
+    assert L.ranphy_receive(None, P(8), P(8), P(8), P(8), None) == -1
+
+
+def test_one_launch_chain_rejects_more_than_8_layers(L):
+    P = ctypes.c_void_p
+    d = _desc(n_layers=9, n_rx=16, dmrs_comb=8, dmrs_td=2)
+    assert L.ranphy_receive(ctypes.byref(d), P(8), P(8), P(8), P(8), None) == -2
 
 
 def test_null_and_misaligned_pointers_rejected(L):
     d = _desc()
-    assert _calls(L, d, 0) == [-1] * 4
-    assert _calls(L, d, 0x1004) == [-1] * 4
+    assert _calls(L, d, 0) == [-1] * 5
+    assert _calls(L, d, 0x1004) == [-1] * 5
     P = ctypes.c_void_p
     assert L.ranphy_chest_ls(ctypes.byref(d), P(8), P(8), P(8), 2, None) == -1  # bad h_res
     assert L.ranphy_mmse_detect(ctypes.byref(d), P(8), P(8), 5, P(8), P(8), P(8), None) == -1
@@ -125,7 +133,7 @@ def test_null_and_misaligned_pointers_rejected(L):
 
 def test_empty_batch_is_a_no_op(L):
     d = _desc(n_slots=0)
-    assert _calls(L, d, 0) == [0] * 4
+    assert _calls(L, d, 0) == [0] * 5
 
 
 def test_binding_refuses_host_tensors(L):
