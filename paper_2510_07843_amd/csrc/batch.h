@@ -34,6 +34,22 @@ constexpr int kBatchFactNP = 36;  // lower-triangle entries of an 8 x 8 factor
 constexpr int kBatchUeOff = 256;
 constexpr int kBatchMaxLayers = 8;
 
+// Complex values per staged pilot row (one pilot index of one occasion: Nr x Nl estimates),
+// made odd so that rows of neighbouring pilots start in different LDS banks.
+__host__ __device__ inline int batch_row_stride(int nr, int nl) { return (nr * nl) | 1; }
+// Two DMRS occasions and at most 4 layers: per subcarrier the tile stages the channel pair
+// (H0, H1 - H0) as float4 per antenna and layer after the pilot rows (from an even complex
+// offset, so 16-byte aligned), padded by one float4 per subcarrier, and the three Gram pieces
+// in the factor area (an odd count of complex values per subcarrier).
+__host__ __device__ inline int batch_pair_stride(int nr, int nl) { return nr * nl + 1; }
+__host__ __device__ inline int batch_gram_stride(int nl) { return (3 * nl * (nl + 1) / 2) | 1; }
+__host__ __device__ inline int batch_pair_base(int rows, int rs) { return (rows * rs + 1) & ~1; }
+__host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk) {
+  if (g.n_occ != 2 || g.n_layers > 4) return false;
+  const int base = batch_pair_base(rows, batch_row_stride(g.n_rx, g.n_layers));
+  return base + 2 * nk * batch_pair_stride(g.n_rx, g.n_layers) <= kBatchLds &&
+         nk * batch_gram_stride(g.n_layers) <= kBatchFactSc * kBatchFactNP;
+}
 // Pilot rows (occasions x pilot indices) a tile of nk subcarriers starting at k0 reads.
 int batch_tile_rows(const Geom& g, int k0, int nk);
 hipError_t launch_batch(void* plan, int blocks, hipStream_t s);

@@ -37,6 +37,37 @@ constexpr float kPivotRel = 16.f * FLT_EPSILON;
 
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// The per-data-symbol tables of a UE's geometry (symbol index and time-interpolation rule),
+// staged in LDS with the pilots: the resource elements of a wave span several data symbols,
+// and reading these lane-varying entries from the geometry in device memory would put a
+// dependent memory round trip before every element's received-signal loads.
+struct SymTab {
+  int dsym[16];
+  int o0[16];
+  int o1[16];
+  float w[16];
+};
+
+// acc += conj(a) b and acc -= a b, acc -= conj(a) b: two fused multiply-adds per component
+__device__ __forceinline__ void cmac_c(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(-a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cmsb(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(-a.x, b.x, acc.x);
+  acc.x = fmaf(a.y, b.y, acc.x);
+  acc.y = fmaf(-a.x, b.y, acc.y);
+  acc.y = fmaf(-a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cmsb_c(float2& acc, float2 a, float2 b) {
+  acc.x = fmaf(-a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(-a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+}
+
 // LLRs of one layer of one RE (compile-time Qm: the values stay in registers).
 template <int QM>
 __device__ __forceinline__ void demap_store(float* __restrict__ dst, float2 xo, float vo) {
@@ -47,17 +78,104 @@ __device__ __forceinline__ void demap_store(float* __restrict__ dst, float2 xo, 
     *reinterpret_cast<float2*>(dst + b) = make_float2(out[b], out[b + 1]);
 }
 
+// Resource element (data symbol d, subcarrier k) from its Gram G = H^H H (lower triangle) and
+// matched filter z = H^H y: G + s2 I = L L^H (Cholesky, Sec. IV, Fig. 4), forward and backward
+// substitution, d_l = || L^-1 e_l ||^2, unbiasing, max-log LLRs into llr[d][k][layer][qm].
 template <int NL>
-__device__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
-                            const float2* __restrict__ lds) {
-  const int NR = g.n_rx, ND = g.n_dsym;
+__device__ __forceinline__ void solve_emit(const Geom& g, float* __restrict__ llr, int d, int k,
+                                           float2 (&G)[NL * (NL + 1) / 2], float2 (&z)[NL],
+                                           float s2) {
+  float gd[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {
+    G[tri(i, i)].x += s2;
+    gd[i] = G[tri(i, i)].x;
+  }
+  bool ok = true;
+  float linv[NL];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {  // Cholesky G = L L^H in place
+    float dj = G[tri(j, j)].x;
+#pragma unroll
+    for (int kk = 0; kk < j; ++kk) {
+      dj = fmaf(-G[tri(j, kk)].x, G[tri(j, kk)].x, dj);
+      dj = fmaf(-G[tri(j, kk)].y, G[tri(j, kk)].y, dj);
+    }
+    ok = ok && (dj > kPivotRel * gd[j]);
+    const float dc = fmaxf(dj, FLT_MIN);
+    const float inv = __builtin_amdgcn_rsqf(dc);  // 1 / L_jj (hardware, about 1 ulp)
+    G[tri(j, j)] = make_float2(dc * inv, 0.f);
+    linv[j] = inv;
+#pragma unroll
+    for (int i = j + 1; i < NL; ++i) {
+      float2 acc = G[tri(i, j)];
+#pragma unroll
+      for (int kk = 0; kk < j; ++kk) {
+        cmsb_c(acc, G[tri(j, kk)], G[tri(i, kk)]);
+      }
+      G[tri(i, j)] = make_float2(acc.x * inv, acc.y * inv);
+    }
+  }
+  float2 wv[NL], xh[NL];
+#pragma unroll
+  for (int i = 0; i < NL; ++i) {  // L w = z
+    float2 acc = z[i];
+#pragma unroll
+    for (int kk = 0; kk < i; ++kk) {
+      cmsb(acc, G[tri(i, kk)], wv[kk]);
+    }
+    wv[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+  }
+#pragma unroll
+  for (int i = NL - 1; i >= 0; --i) {  // L^H x = w
+    float2 acc = wv[i];
+#pragma unroll
+    for (int kk = i + 1; kk < NL; ++kk) {
+      cmsb_c(acc, G[tri(kk, i)], xh[kk]);
+    }
+    xh[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+  }
+  float* __restrict__ dst = llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2, unbias, demap
+    float2 uu[NL];
+    uu[l] = make_float2(linv[l], 0.f);
+    float acc2 = linv[l] * linv[l];
+#pragma unroll
+    for (int i = l + 1; i < NL; ++i) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int kk = l; kk < i; ++kk) {
+        cmsb(acc, G[tri(i, kk)], uu[kk]);
+      }
+      uu[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
+      acc2 += uu[i].x * uu[i].x + uu[i].y * uu[i].y;
+    }
+    const float sd = s2 * acc2;
+    const float im = __builtin_amdgcn_rcpf(1.f - sd);
+    const float2 xo = ok ? make_float2(xh[l].x * im, xh[l].y * im)
+                         : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    const float vo = ok ? sd * im : __builtin_inff();
+    switch (g.qm) {  // uniform over the item
+      case 2: demap_store<2>(dst + l * 2, xo, vo); break;
+      case 4: demap_store<4>(dst + l * 4, xo, vo); break;
+      case 6: demap_store<6>(dst + l * 6, xo, vo); break;
+      default: demap_store<8>(dst + l * 8, xo, vo); break;
+    }
+  }
+}
+
+template <int NL>
+__device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+                            const float2* __restrict__ lds, const SymTab& tab) {
+  const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
   for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
     const int d = e / nk;
     const int k = k0 + (e - d * nk);
-    const int s = g.dsym[d];
-    const int o0 = g.t_o0[d], o1 = g.t_o1[d];
-    const float w = g.t_w[d];
+    const int s = tab.dsym[d];
+    const int o0 = tab.o0[d], o1 = tab.o1[d];
+    const float w = tab.w[d];
     int r0[NL], r1[NL];
     float a[NL];
 #pragma unroll
@@ -75,124 +193,126 @@ __device__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk, int
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
     const float2* __restrict__ yrow = u.rx + ((int64_t)s * g.n_sc + k) * NR;
     for (int r = 0; r < NR; ++r) {
+      const float2 y = yrow[r];
       float2 hr[NL];
 #pragma unroll
       for (int p = 0; p < NL; ++p) {
         const float2* b = lds + r * NL + p;
-        const float2 v0 = b[(o0 * nj + r0[p]) * NR * NL], v1 = b[(o0 * nj + r1[p]) * NR * NL];
+        const float2 v0 = b[(o0 * nj + r0[p]) * RS], v1 = b[(o0 * nj + r1[p]) * RS];
         float2 v = make_float2(v0.x + a[p] * (v1.x - v0.x), v0.y + a[p] * (v1.y - v0.y));
         if (o1 != o0) {
-          const float2 u0 = b[(o1 * nj + r0[p]) * NR * NL], u1 = b[(o1 * nj + r1[p]) * NR * NL];
+          const float2 u0 = b[(o1 * nj + r0[p]) * RS], u1 = b[(o1 * nj + r1[p]) * RS];
           const float2 vv = make_float2(u0.x + a[p] * (u1.x - u0.x), u0.y + a[p] * (u1.y - u0.y));
           v = make_float2(v.x + w * (vv.x - v.x), v.y + w * (vv.y - v.y));
         }
         hr[p] = v;
       }
-      const float2 y = yrow[r];
 #pragma unroll
       for (int i = 0; i < NL; ++i) {
-        const float2 m = cmulc(hr[i], y);
-        z[i].x += m.x;
-        z[i].y += m.y;
+        cmac_c(z[i], hr[i], y);
 #pragma unroll
-        for (int j = 0; j <= i; ++j) {
-          const float2 gg = cmulc(hr[i], hr[j]);
-          G[tri(i, j)].x += gg.x;
-          G[tri(i, j)].y += gg.y;
-        }
+        for (int j = 0; j <= i; ++j) cmac_c(G[tri(i, j)], hr[i], hr[j]);
       }
     }
-    float gd[NL];
+    solve_emit<NL>(g, u.llr, d, k, G, z, s2);
+  }
+}
+
+// Two DMRS occasions, up to 4 layers.  The channel at a data symbol is H0 + t (H1 - H0) with
+// t from the time rule (0 or 1 before the first or after the last occasion), so its Gram is
+// (1-t)^2 A + t(1-t) S + t^2 C with A = H0^H H0, C = H1^H H1 and S = H0^H H1 + H1^H H0, the
+// same quantity with the antenna sums taken once per subcarrier instead of per resource
+// element.  The tile stages, per subcarrier, H0 and D = H1 - H0 (interpolated in frequency
+// once; float4 (H0, D) per antenna and layer in pair[]) and A, S, C (in gram[]); each
+// resource element then blends its Gram, forms z = (H0 + t D)^H y from the staged pairs and
+// finishes as the other paths do.
+template <int NL>
+__device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+                                 const float2* __restrict__ rows, float4* __restrict__ pair,
+                                 float2* __restrict__ gram, const SymTab& tab) {
+  constexpr int NP = NL * (NL + 1) / 2;
+  const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
+  const int PS = batch_pair_stride(NR, NL), GS = batch_gram_stride(NL);
+  for (int f = threadIdx.x; f < nk * NR; f += blockDim.x) {  // (subcarrier, antenna)
+    const int kk = f / NR;
+    const int r = f - kk * NR;
+    const int k = k0 + kk;
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-      G[tri(i, i)].x += s2;
-      gd[i] = G[tri(i, i)].x;
+    for (int p = 0; p < NL; ++p) {
+      int j0, j1;
+      float a;
+      freq_rule(g, p, k, j0, j1, a);
+      const float2* b = rows + r * NL + p;
+      const float2 v0 = b[(j0 - jlo) * RS], v1 = b[(j1 - jlo) * RS];
+      const float2 u0 = b[(nj + j0 - jlo) * RS], u1 = b[(nj + j1 - jlo) * RS];
+      const float2 h0 = make_float2(v0.x + a * (v1.x - v0.x), v0.y + a * (v1.y - v0.y));
+      const float2 h1 = make_float2(u0.x + a * (u1.x - u0.x), u0.y + a * (u1.y - u0.y));
+      pair[kk * PS + r * NL + p] = make_float4(h0.x, h0.y, h1.x - h0.x, h1.y - h0.y);
     }
-    bool ok = true;
-    float linv[NL];
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < nk * NP; f += blockDim.x) {  // (subcarrier, Gram entry)
+    const int kk = f / NP;
+    const int e = f - kk * NP;
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= e) ++i;
+    const int j = e - i * (i + 1) / 2;
+    float2 A = make_float2(0.f, 0.f), S = A, C = A;
+    const float4* q = pair + kk * PS;
+    for (int r = 0; r < NR; ++r) {
+      const float4 qi = q[r * NL + i], qj = q[r * NL + j];
+      const float2 h0i = make_float2(qi.x, qi.y), h0j = make_float2(qj.x, qj.y);
+      const float2 h1i = make_float2(qi.x + qi.z, qi.y + qi.w);
+      const float2 h1j = make_float2(qj.x + qj.z, qj.y + qj.w);
+      cmac_c(A, h0i, h0j);
+      cmac_c(C, h1i, h1j);
+      cmac_c(S, h0i, h1j);
+      cmac_c(S, h1i, h0j);
+    }
+    float2* gg = gram + kk * GS;
+    gg[e] = A;
+    gg[NP + e] = S;
+    gg[2 * NP + e] = C;
+  }
+  __syncthreads();
+  const float s2 = *u.nv;
+  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {  // resource elements
+    const int d = e / nk;
+    const int kk = e - d * nk;
+    const int k = k0 + kk;
+    const int o0 = tab.o0[d], o1 = tab.o1[d];
+    const float t = o0 == o1 ? (float)o0 : tab.w[d];
+    const float w0 = (1.f - t) * (1.f - t), w1 = t * (1.f - t), w2 = t * t;
+    const float2* gg = gram + kk * GS;
+    float2 G[NP], z[NL];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) {  // Cholesky G = L L^H in place
-      float dj = G[tri(j, j)].x;
+    for (int i = 0; i < NP; ++i) {
+      const float2 A = gg[i], S = gg[NP + i], C = gg[2 * NP + i];
+      G[i] = make_float2(w0 * A.x + w1 * S.x + w2 * C.x, w0 * A.y + w1 * S.y + w2 * C.y);
+    }
 #pragma unroll
-      for (int kk = 0; kk < j; ++kk) dj -= G[tri(j, kk)].x * G[tri(j, kk)].x + G[tri(j, kk)].y * G[tri(j, kk)].y;
-      ok = ok && (dj > kPivotRel * gd[j]);
-      const float ljj = sqrtf(fmaxf(dj, FLT_MIN));
-      const float inv = 1.f / ljj;
-      G[tri(j, j)] = make_float2(ljj, 0.f);
-      linv[j] = inv;
+    for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
+    const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
+    const float4* q = pair + kk * PS;
+#pragma unroll 8
+    for (int r = 0; r < NR; ++r) {
+      const float2 y = yrow[r];
 #pragma unroll
-      for (int i = j + 1; i < NL; ++i) {
-        float2 acc = G[tri(i, j)];
-#pragma unroll
-        for (int kk = 0; kk < j; ++kk) {
-          const float2 m = cmulc(G[tri(j, kk)], G[tri(i, kk)]);
-          acc.x -= m.x;
-          acc.y -= m.y;
-        }
-        G[tri(i, j)] = make_float2(acc.x * inv, acc.y * inv);
+      for (int p = 0; p < NL; ++p) {
+        const float4 v = q[r * NL + p];
+        const float2 h = make_float2(v.x + t * v.z, v.y + t * v.w);
+        cmac_c(z[p], h, y);
       }
     }
-    float2 wv[NL], xh[NL];
-#pragma unroll
-    for (int i = 0; i < NL; ++i) {  // L w = z
-      float2 acc = z[i];
-#pragma unroll
-      for (int kk = 0; kk < i; ++kk) {
-        const float2 m = cmul(G[tri(i, kk)], wv[kk]);
-        acc.x -= m.x;
-        acc.y -= m.y;
-      }
-      wv[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
-    }
-#pragma unroll
-    for (int i = NL - 1; i >= 0; --i) {  // L^H x = w
-      float2 acc = wv[i];
-#pragma unroll
-      for (int kk = i + 1; kk < NL; ++kk) {
-        const float2 m = cmulc(G[tri(kk, i)], xh[kk]);
-        acc.x -= m.x;
-        acc.y -= m.y;
-      }
-      xh[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
-    }
-    float* __restrict__ dst = u.llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2, unbias, demap
-      float2 uu[NL];
-      uu[l] = make_float2(linv[l], 0.f);
-      float acc2 = linv[l] * linv[l];
-#pragma unroll
-      for (int i = l + 1; i < NL; ++i) {
-        float2 acc = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int kk = l; kk < i; ++kk) {
-          const float2 m = cmul(G[tri(i, kk)], uu[kk]);
-          acc.x -= m.x;
-          acc.y -= m.y;
-        }
-        uu[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
-        acc2 += uu[i].x * uu[i].x + uu[i].y * uu[i].y;
-      }
-      const float sd = s2 * acc2;
-      const float im = 1.f / (1.f - sd);
-      const float2 xo = ok ? make_float2(xh[l].x * im, xh[l].y * im)
-                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-      const float vo = ok ? sd * im : __builtin_inff();
-      switch (g.qm) {  // uniform over the item
-        case 2: demap_store<2>(dst + l * 2, xo, vo); break;
-        case 4: demap_store<4>(dst + l * 4, xo, vo); break;
-        case 6: demap_store<6>(dst + l * 6, xo, vo); break;
-        default: demap_store<8>(dst + l * 8, xo, vo); break;
-      }
-    }
+    solve_emit<NL>(g, u.llr, d, k, G, z, s2);
   }
 }
 
 // Channel value of port p at antenna r for the subcarrier whose interpolation rows and
-// weight are (r0, r1, a), one occasion: rows[j][r][p].
-__device__ __forceinline__ float2 row_interp(const float2* __restrict__ rows, int NR, int NL,
+// weight are (r0, r1, a), one occasion: rows[j][r][p], RS complex values per row.
+__device__ __forceinline__ float2 row_interp(const float2* __restrict__ rows, int RS, int NL,
                                              int r0, int r1, float a, int r, int p) {
-  const float2 v0 = rows[(r0 * NR + r) * NL + p], v1 = rows[(r1 * NR + r) * NL + p];
+  const float2 v0 = rows[r0 * RS + r * NL + p], v1 = rows[r1 * RS + r * NL + p];
   return make_float2(v0.x + a * (v1.x - v0.x), v0.y + a * (v1.y - v0.y));
 }
 
@@ -200,11 +320,11 @@ __device__ __forceinline__ float2 row_interp(const float2* __restrict__ rows, in
 // tile's subcarriers into LDS.  fac[kk][tri(i, j)] holds L, aux[kk][0..NL) 1 / L_ii,
 // aux[kk][NL..2NL) d, aux[kk][2NL] 1 where the factorisation succeeded, else 0.
 template <int NL>
-__device__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
+__device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
                             const float2* __restrict__ rows, float2* __restrict__ fac,
                             float* __restrict__ aux) {
   constexpr int NP = NL * (NL + 1) / 2;
-  const int NR = g.n_rx;
+  const int NR = g.n_rx, RS = batch_row_stride(NR, NL);
   for (int f = threadIdx.x; f < nk * NP; f += blockDim.x) {
     const int kk = f / NP;
     const int e = f - kk * NP;
@@ -219,11 +339,9 @@ __device__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int
     ri0 -= jlo; ri1 -= jlo; rj0 -= jlo; rj1 -= jlo;
     float2 acc = make_float2(0.f, 0.f);
     for (int r = 0; r < NR; ++r) {  // the order of the per-RE path's sums
-      const float2 hi = row_interp(rows, NR, NL, ri0, ri1, ai, r, i);
-      const float2 hj = row_interp(rows, NR, NL, rj0, rj1, aj, r, j);
-      const float2 gg = cmulc(hi, hj);
-      acc.x += gg.x;
-      acc.y += gg.y;
+      const float2 hi = row_interp(rows, RS, NL, ri0, ri1, ai, r, i);
+      const float2 hj = row_interp(rows, RS, NL, rj0, rj1, aj, r, j);
+      cmac_c(acc, hi, hj);
     }
     fac[kk * kBatchFactNP + e] = acc;
   }
@@ -256,9 +374,7 @@ __device__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int
         float2 acc = G[tri(i, j)];
 #pragma unroll
         for (int kq = 0; kq < j; ++kq) {
-          const float2 m = cmulc(G[tri(j, kq)], G[tri(i, kq)]);
-          acc.x -= m.x;
-          acc.y -= m.y;
+          cmsb_c(acc, G[tri(j, kq)], G[tri(i, kq)]);
         }
         G[tri(i, j)] = make_float2(acc.x * inv, acc.y * inv);
       }
@@ -274,9 +390,7 @@ __device__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
         for (int kq = l; kq < i; ++kq) {
-          const float2 m = cmul(G[tri(i, kq)], uu[kq]);
-          acc.x -= m.x;
-          acc.y -= m.y;
+          cmsb(acc, G[tri(i, kq)], uu[kq]);
         }
         uu[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
         acc2 += uu[i].x * uu[i].x + uu[i].y * uu[i].y;
@@ -294,11 +408,12 @@ __device__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int
 // One occasion, per resource element with the staged factor: matched filter, substitutions,
 // unbiasing, LLRs.
 template <int NL>
-__device__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
+__device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
                                  const float2* __restrict__ rows,
-                                 const float2* __restrict__ fac, const float* __restrict__ aux) {
+                                 const float2* __restrict__ fac, const float* __restrict__ aux,
+                                 const SymTab& tab) {
   constexpr int NP = NL * (NL + 1) / 2;
-  const int NR = g.n_rx, ND = g.n_dsym;
+  const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
   for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
     const int d = e / nk;
@@ -316,15 +431,12 @@ __device__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk
     float2 z[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
-    const float2* __restrict__ yrow = u.rx + ((int64_t)g.dsym[d] * g.n_sc + k) * NR;
+    const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
+#pragma unroll 8
     for (int r = 0; r < NR; ++r) {
       const float2 y = yrow[r];
 #pragma unroll
-      for (int i = 0; i < NL; ++i) {
-        const float2 m = cmulc(row_interp(rows, NR, NL, r0[i], r1[i], a[i], r, i), y);
-        z[i].x += m.x;
-        z[i].y += m.y;
-      }
+      for (int i = 0; i < NL; ++i) cmac_c(z[i], row_interp(rows, RS, NL, r0[i], r1[i], a[i], r, i), y);
     }
     const float2* L = fac + kk * kBatchFactNP;
     const float* ax = aux + kk * (2 * kBatchMaxLayers + 1);
@@ -335,9 +447,7 @@ __device__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk
       float2 acc = z[i];
 #pragma unroll
       for (int kq = 0; kq < i; ++kq) {
-        const float2 m = cmul(L[tri(i, kq)], wv[kq]);
-        acc.x -= m.x;
-        acc.y -= m.y;
+        cmsb(acc, L[tri(i, kq)], wv[kq]);
       }
       wv[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
     }
@@ -346,9 +456,7 @@ __device__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk
       float2 acc = wv[i];
 #pragma unroll
       for (int kq = i + 1; kq < NL; ++kq) {
-        const float2 m = cmulc(L[tri(kq, i)], xh[kq]);
-        acc.x -= m.x;
-        acc.y -= m.y;
+        cmsb_c(acc, L[tri(kq, i)], xh[kq]);
       }
       xh[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
     }
@@ -370,22 +478,12 @@ __device__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk
   }
 }
 
-template <int NL>
-__device__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
-                             const float2* rows, float2* fac, float* aux) {
-  if (g.n_occ == 1) {
-    factor_tile<NL>(u, g, k0, nk, jlo, rows, fac, aux);
-    detect_tile_fact<NL>(u, g, k0, nk, jlo, rows, fac, aux);
-  } else {
-    detect_tile<NL>(u, g, k0, nk, jlo, nj, rows);
-  }
-}
-
 // The LS estimate (Sec. III-B) of every pilot the tile k0 .. k0 + nk - 1 interpolates from,
-// every occasion, into rows[o][j - jlo][r][p]; returns jlo and the pilot count nj.  Ends with
-// a barrier.
+// every occasion, into rows[o][j - jlo][r][p] (rows of batch_row_stride values), and the
+// symbol tables into tab; returns jlo and the pilot count nj.  Ends with a barrier.
 __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, int k0, int nk,
-                             float2* __restrict__ rows, int& jlo, int& nj) {
+                                             float2* __restrict__ rows, SymTab& tab, int& jlo,
+                                             int& nj) {
   const int C = g.comb, T = g.td, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot;
   // pilot range of the tile: a port's pilot indices do not decrease with the subcarrier
   int lo = J, hi = 0;
@@ -399,41 +497,72 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
   }
   jlo = lo;
   nj = hi - lo + 1;
-  const int n_ls = g.n_occ * nj * NR * NL;
+  const int per_occ = nj * NR * NL, RS = batch_row_stride(NR, NL);
   const float inv_t = 1.f / (float)T;
-  for (int f = threadIdx.x; f < n_ls; f += blockDim.x) {
-    const int p = f % NL;
-    const int r = (f / NL) % NR;
-    const int jj = (f / (NL * NR)) % nj;
-    const int o = f / (NL * NR * nj);
-    const int j = jlo + jj;
-    const int k = C * j + (p & (C - 1));
-    float2 acc = make_float2(0.f, 0.f);
-    if (k < g.n_sc) {
-      for (int t = 0; t < T; ++t) {
-        const float2 y = u.rx[((int64_t)(g.sym0[o] + t) * g.n_sc + k) * NR + r];
-        const float2 q = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
-        const float2 m = cmulc(q, y);  // y conj(q)
-        acc.x += m.x;
-        acc.y += m.y;
+  for (int o = 0; o < g.n_occ; ++o) {  // uniform: the occasion's symbol is a scalar load
+    const float2* __restrict__ rx0 = u.rx + (int64_t)g.sym0[o] * g.n_sc * NR;
+#pragma unroll 4
+    for (int f = threadIdx.x; f < per_occ; f += blockDim.x) {
+      const int p = f % NL;
+      const int r = (f / NL) % NR;
+      const int jj = f / (NL * NR);
+      const int j = jlo + jj;
+      const int k = C * j + (p & (C - 1));
+      float2 acc = make_float2(0.f, 0.f);
+      if (k < g.n_sc) {
+        for (int t = 0; t < T; ++t) {
+          const float2 y = rx0[((int64_t)t * g.n_sc + k) * NR + r];
+          const float2 q = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
+          cmac_c(acc, q, y);  // y conj(q)
+        }
       }
+      rows[(o * nj + jj) * RS + r * NL + p] = make_float2(acc.x * inv_t, acc.y * inv_t);
     }
-    rows[f] = make_float2(acc.x * inv_t, acc.y * inv_t);
+  }
+  if (threadIdx.x < g.n_dsym) {
+    const int d = threadIdx.x;
+    tab.dsym[d] = g.dsym[d];
+    tab.o0[d] = g.t_o0[d];
+    tab.o1[d] = g.t_o1[d];
+    tab.w[d] = g.t_w[d];
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ void process_any(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
-                            const float2* rows, float2* fac, float* aux) {
+// One tile of nk subcarriers starting at k0: pilots staged, then the path for the DMRS layout.
+template <int NL>
+__device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk,
+                                             float2* rows, float2* fac, float* aux,
+                                             SymTab& tab) {
+  int jlo, nj;
+  stage_pilots(u, g, k0, nk, rows, tab, jlo, nj);
+  if (g.n_occ == 1) {
+    factor_tile<NL>(u, g, k0, nk, jlo, rows, fac, aux);
+    detect_tile_fact<NL>(u, g, k0, nk, jlo, rows, fac, aux, tab);
+    return;
+  }
+  if constexpr (NL <= 4) {
+    if (batch_pair_fits(g, g.n_occ * nj, nk)) {
+      float4* pair = reinterpret_cast<float4*>(
+          rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
+      detect_tile_pair<NL>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
+      return;
+    }
+  }
+  detect_tile<NL>(u, g, k0, nk, jlo, nj, rows, tab);
+}
+
+__device__ __forceinline__ void process_any(const BatchUe& u, const Geom& g, int k0, int nk,
+                                            float2* rows, float2* fac, float* aux, SymTab& tab) {
   switch (g.n_layers) {  // uniform over the block
-    case 1: process_tile<1>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    case 2: process_tile<2>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    case 3: process_tile<3>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    case 4: process_tile<4>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    case 5: process_tile<5>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    case 6: process_tile<6>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    case 7: process_tile<7>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
-    default: process_tile<8>(u, g, k0, nk, jlo, nj, rows, fac, aux); break;
+    case 1: process_tile<1>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 2: process_tile<2>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 3: process_tile<3>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 4: process_tile<4>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 5: process_tile<5>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 6: process_tile<6>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 7: process_tile<7>(u, g, k0, nk, rows, fac, aux, tab); break;
+    default: process_tile<8>(u, g, k0, nk, rows, fac, aux, tab); break;
   }
 }
 
@@ -443,9 +572,10 @@ __global__ void batch_reset_kernel(BatchHdr* __restrict__ hdr) {
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) batch_kernel(
     char* __restrict__ plan) {
-  __shared__ float2 lds[kBatchLds];
+  __shared__ __align__(16) float2 lds[kBatchLds];
   __shared__ float2 fac[kBatchFactSc * kBatchFactNP];
   __shared__ float aux[kBatchFactSc * (2 * kBatchMaxLayers + 1)];
+  __shared__ SymTab tab;
   __shared__ int s_item;
   BatchHdr* hdr = reinterpret_cast<BatchHdr*>(plan);
   const BatchUe* ues = reinterpret_cast<const BatchUe*>(plan + kBatchUeOff);
@@ -460,9 +590,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     const BatchItem item = items[it];
     const BatchUe& u = ues[item.ue];
     const Geom& g = u.g;  // read in place (a private copy indexed at run time would spill)
-    int jlo, nj;
-    stage_pilots(u, g, item.k0, item.nk, lds, jlo, nj);
-    process_any(u, g, item.k0, item.nk, jlo, nj, lds, fac, aux);
+    process_any(u, g, item.k0, item.nk, lds, fac, aux, tab);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -473,9 +601,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
                const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
-  __shared__ float2 lds[kBatchLds];
+  __shared__ __align__(16) float2 lds[kBatchLds];
   __shared__ float2 fac[kBatchFactSc * kBatchFactNP];
   __shared__ float aux[kBatchFactSc * (2 * kBatchMaxLayers + 1)];
+  __shared__ SymTab tab;
   const int ntiles = (g.n_sc + nk - 1) / nk;
   const int slot = blockIdx.x / ntiles;
   const int k0 = (blockIdx.x - slot * ntiles) * nk;
@@ -486,28 +615,32 @@ receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__
   u.nv = nvar + slot;
   u.llr = llr + (int64_t)slot * g.n_dsym * g.n_sc * g.n_layers * g.qm;
   const int n = min(nk, g.n_sc - k0);
-  int jlo, nj;
-  stage_pilots(u, g, k0, n, lds, jlo, nj);
-  process_any(u, g, k0, n, jlo, nj, lds, fac, aux);
+  process_any(u, g, k0, n, lds, fac, aux, tab);
 }
 
 }  // namespace
 
 // Tile width of the one-launch chain: about tile_re resource elements, at most kBatchFactSc
-// subcarriers, and pilot rows that fit the block's LDS for every tile.
+// subcarriers; with two occasions and at most 4 layers the widest (not under 8 subcarriers)
+// whose channel pairs fit the block's LDS at every tile, else pilot rows that fit.
 int receive_tile(const Geom& g, int tile_re) {
-  int nk = tile_re / g.n_dsym;
-  nk = nk < 1 ? 1 : (nk > kBatchFactSc ? kBatchFactSc : nk);
-  const int per = g.n_rx * g.n_layers;
-  for (;;) {
-    int worst = 0;
+  int want = tile_re / g.n_dsym;
+  want = want < 1 ? 1 : (want > kBatchFactSc ? kBatchFactSc : want);
+  const int per = batch_row_stride(g.n_rx, g.n_layers);
+  auto all_fit = [&](int nk, bool pair) {
     for (int k0 = 0; k0 < g.n_sc; k0 += nk) {
       const int n = g.n_sc - k0 < nk ? g.n_sc - k0 : nk;
-      const int r = batch_tile_rows(g, k0, n);
-      worst = r > worst ? r : worst;
+      const int rows = batch_tile_rows(g, k0, n);
+      if (pair ? !batch_pair_fits(g, rows, n) : rows * per > kBatchLds) return false;
     }
-    if (worst * per <= kBatchLds || nk == 1) return worst * per <= kBatchLds ? nk : 0;
-    nk = (nk + 1) / 2;
+    return true;
+  };
+  if (g.n_occ == 2 && g.n_layers <= 4)
+    for (int nk = want; nk >= 8; nk = (nk + 1) / 2)
+      if (all_fit(nk, true)) return nk;
+  for (int nk = want;; nk = (nk + 1) / 2) {
+    if (all_fit(nk, false)) return nk;
+    if (nk == 1) return 0;
   }
 }
 

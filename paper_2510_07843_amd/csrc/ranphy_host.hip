@@ -351,11 +351,17 @@ static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<
     recs[u].nv = e.noise_var;
     recs[u].llr = e.llr;
     // tiles of about tile_re resource elements whose pilot estimates fit the block's LDS
-    const int per = g.n_rx * g.n_layers;
+    const int per = ranphy::batch_row_stride(g.n_rx, g.n_layers);
     int want = std::max(1, tile_re / g.n_dsym);
     if (g.n_occ == 1) want = std::min(want, ranphy::kBatchFactSc);
     for (int k0 = 0; k0 < g.n_sc;) {
       int nk = std::min(want, g.n_sc - k0);
+      // two occasions, up to 4 layers: the widest tile (not under 8 subcarriers) whose
+      // channel pairs fit; otherwise pilot rows that fit
+      int np = nk;
+      while (np >= 8 && !ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np))
+        np = (np + 1) / 2;
+      if (np >= 8 && ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np)) nk = np;
       while (nk > 1 && ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) nk = (nk + 1) / 2;
       if (ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) return RANPHY_ERR_UNSUPPORTED;
       // class: layers, modulation, antennas
