@@ -44,11 +44,28 @@ __host__ __device__ inline int batch_row_stride(int nr, int nl) { return (nr * n
 __host__ __device__ inline int batch_pair_stride(int nr, int nl) { return nr * nl + 1; }
 __host__ __device__ inline int batch_gram_stride(int nl) { return (3 * nl * (nl + 1) / 2) | 1; }
 __host__ __device__ inline int batch_pair_base(int rows, int rs) { return (rows * rs + 1) & ~1; }
-__host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk) {
+// LDS capacities of a block serving up to MAXNL layers: complex values of pilot rows and
+// channel pairs (rows), complex values of factors or Gram pieces (fac), the factor and aux
+// strides per subcarrier, and the subcarriers of a one-occasion tile (fsc).  The 4-layer form
+// fits 4 blocks per CU; the 8-layer form 3.
+template <int MAXNL>
+struct TileCap;
+template <>
+struct TileCap<8> {
+  static constexpr int rows = kBatchLds, fac = kBatchFactSc * kBatchFactNP, fnp = kBatchFactNP,
+                       aux = 2 * 8 + 1, fsc = kBatchFactSc;
+};
+template <>
+struct TileCap<4> {
+  static constexpr int rows = 3776, fac = 1024, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
+};
+
+__host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk, int cap_rows,
+                                                int cap_fac) {
   if (g.n_occ != 2 || g.n_layers > 4) return false;
   const int base = batch_pair_base(rows, batch_row_stride(g.n_rx, g.n_layers));
-  return base + 2 * nk * batch_pair_stride(g.n_rx, g.n_layers) <= kBatchLds &&
-         nk * batch_gram_stride(g.n_layers) <= kBatchFactSc * kBatchFactNP;
+  return base + 2 * nk * batch_pair_stride(g.n_rx, g.n_layers) <= cap_rows &&
+         nk * batch_gram_stride(g.n_layers) <= cap_fac;
 }
 // Pilot rows (occasions x pilot indices) a tile of nk subcarriers starting at k0 reads.
 int batch_tile_rows(const Geom& g, int k0, int nk);

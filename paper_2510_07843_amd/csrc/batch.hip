@@ -48,6 +48,21 @@ struct SymTab {
   float w[16];
 };
 
+// n / d for 0 <= n < 2^22 by a float reciprocal and one correction step: an integer division
+// by a run-time divisor costs tens of instructions, and the tile loops take one per element.
+// The float quotient is exact or one below (n is exact as a float, the reciprocal within half
+// an ulp), so a single remainder test fixes it.
+struct FastDiv {
+  int d;
+  float inv;
+  __device__ explicit FastDiv(int dd) : d(dd), inv(1.f / (float)dd) {}
+  __device__ __forceinline__ int operator()(int n) const {
+    int q = (int)((float)n * inv);
+    if (n - q * d >= d) ++q;
+    return q;
+  }
+};
+
 // acc += conj(a) b and acc -= a b, acc -= conj(a) b: two fused multiply-adds per component
 __device__ __forceinline__ void cmac_c(float2& acc, float2 a, float2 b) {
   acc.x = fmaf(a.x, b.x, acc.x);
@@ -170,8 +185,9 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
                             const float2* __restrict__ lds, const SymTab& tab) {
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
+  const FastDiv by_nk(nk);
   for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
-    const int d = e / nk;
+    const int d = by_nk(e);
     const int k = k0 + (e - d * nk);
     const int s = tab.dsym[d];
     const int o0 = tab.o0[d], o1 = tab.o1[d];
@@ -233,8 +249,9 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
   constexpr int NP = NL * (NL + 1) / 2;
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const int PS = batch_pair_stride(NR, NL), GS = batch_gram_stride(NL);
+  const FastDiv by_nr(NR);
   for (int f = threadIdx.x; f < nk * NR; f += blockDim.x) {  // (subcarrier, antenna)
-    const int kk = f / NR;
+    const int kk = by_nr(f);
     const int r = f - kk * NR;
     const int k = k0 + kk;
 #pragma unroll
@@ -276,8 +293,9 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
   }
   __syncthreads();
   const float s2 = *u.nv;
+  const FastDiv by_nk(nk);
   for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {  // resource elements
-    const int d = e / nk;
+    const int d = by_nk(e);
     const int kk = e - d * nk;
     const int k = k0 + kk;
     const int o0 = tab.o0[d], o1 = tab.o1[d];
@@ -319,7 +337,7 @@ __device__ __forceinline__ float2 row_interp(const float2* __restrict__ rows, in
 // One occasion: Gram, Cholesky factor, reciprocal diagonal and d = diag(G^-1) of each of the
 // tile's subcarriers into LDS.  fac[kk][tri(i, j)] holds L, aux[kk][0..NL) 1 / L_ii,
 // aux[kk][NL..2NL) d, aux[kk][2NL] 1 where the factorisation succeeded, else 0.
-template <int NL>
+template <int NL, class CAP>
 __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
                             const float2* __restrict__ rows, float2* __restrict__ fac,
                             float* __restrict__ aux) {
@@ -343,14 +361,14 @@ __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int
       const float2 hj = row_interp(rows, RS, NL, rj0, rj1, aj, r, j);
       cmac_c(acc, hi, hj);
     }
-    fac[kk * kBatchFactNP + e] = acc;
+    fac[kk * CAP::fnp + e] = acc;
   }
   __syncthreads();
   const float s2 = *u.nv;
   for (int kk = threadIdx.x; kk < nk; kk += blockDim.x) {
     float2 G[NP];
 #pragma unroll
-    for (int e = 0; e < NP; ++e) G[e] = fac[kk * kBatchFactNP + e];
+    for (int e = 0; e < NP; ++e) G[e] = fac[kk * CAP::fnp + e];
     float gd[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
@@ -379,7 +397,7 @@ __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int
         G[tri(i, j)] = make_float2(acc.x * inv, acc.y * inv);
       }
     }
-    float* ax = aux + kk * (2 * kBatchMaxLayers + 1);
+    float* ax = aux + kk * CAP::aux;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2
       float2 uu[NL];
@@ -400,14 +418,14 @@ __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int
     }
     ax[2 * NL] = ok ? 1.f : 0.f;
 #pragma unroll
-    for (int e = 0; e < NP; ++e) fac[kk * kBatchFactNP + e] = G[e];
+    for (int e = 0; e < NP; ++e) fac[kk * CAP::fnp + e] = G[e];
   }
   __syncthreads();
 }
 
 // One occasion, per resource element with the staged factor: matched filter, substitutions,
 // unbiasing, LLRs.
-template <int NL>
+template <int NL, class CAP>
 __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
                                  const float2* __restrict__ rows,
                                  const float2* __restrict__ fac, const float* __restrict__ aux,
@@ -415,8 +433,9 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
   constexpr int NP = NL * (NL + 1) / 2;
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
+  const FastDiv by_nk(nk);
   for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
-    const int d = e / nk;
+    const int d = by_nk(e);
     const int kk = e - d * nk;
     const int k = k0 + kk;
     int r0[NL], r1[NL];
@@ -438,8 +457,8 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
 #pragma unroll
       for (int i = 0; i < NL; ++i) cmac_c(z[i], row_interp(rows, RS, NL, r0[i], r1[i], a[i], r, i), y);
     }
-    const float2* L = fac + kk * kBatchFactNP;
-    const float* ax = aux + kk * (2 * kBatchMaxLayers + 1);
+    const float2* L = fac + kk * CAP::fnp;
+    const float* ax = aux + kk * CAP::aux;
     const bool ok = ax[2 * NL] != 0.f;
     float2 wv[NL], xh[NL];
 #pragma unroll
@@ -499,13 +518,15 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
   nj = hi - lo + 1;
   const int per_occ = nj * NR * NL, RS = batch_row_stride(NR, NL);
   const float inv_t = 1.f / (float)T;
+  const FastDiv by_nl(NL), by_nr(NR);
   for (int o = 0; o < g.n_occ; ++o) {  // uniform: the occasion's symbol is a scalar load
     const float2* __restrict__ rx0 = u.rx + (int64_t)g.sym0[o] * g.n_sc * NR;
 #pragma unroll 4
     for (int f = threadIdx.x; f < per_occ; f += blockDim.x) {
-      const int p = f % NL;
-      const int r = (f / NL) % NR;
-      const int jj = f / (NL * NR);
+      const int fl = by_nl(f);
+      const int p = f - fl * NL;
+      const int jj = by_nr(fl);
+      const int r = fl - jj * NR;
       const int j = jlo + jj;
       const int k = C * j + (p & (C - 1));
       float2 acc = make_float2(0.f, 0.f);
@@ -530,19 +551,19 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
 }
 
 // One tile of nk subcarriers starting at k0: pilots staged, then the path for the DMRS layout.
-template <int NL>
+template <int NL, class CAP>
 __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk,
                                              float2* rows, float2* fac, float* aux,
                                              SymTab& tab) {
   int jlo, nj;
   stage_pilots(u, g, k0, nk, rows, tab, jlo, nj);
   if (g.n_occ == 1) {
-    factor_tile<NL>(u, g, k0, nk, jlo, rows, fac, aux);
-    detect_tile_fact<NL>(u, g, k0, nk, jlo, rows, fac, aux, tab);
+    factor_tile<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux);
+    detect_tile_fact<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux, tab);
     return;
   }
   if constexpr (NL <= 4) {
-    if (batch_pair_fits(g, g.n_occ * nj, nk)) {
+    if (batch_pair_fits(g, g.n_occ * nj, nk, CAP::rows, CAP::fac)) {
       float4* pair = reinterpret_cast<float4*>(
           rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
       detect_tile_pair<NL>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
@@ -552,17 +573,27 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
   detect_tile<NL>(u, g, k0, nk, jlo, nj, rows, tab);
 }
 
+template <int MAXNL>
 __device__ __forceinline__ void process_any(const BatchUe& u, const Geom& g, int k0, int nk,
                                             float2* rows, float2* fac, float* aux, SymTab& tab) {
+  using CAP = TileCap<MAXNL>;
   switch (g.n_layers) {  // uniform over the block
-    case 1: process_tile<1>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 2: process_tile<2>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 3: process_tile<3>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 4: process_tile<4>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 5: process_tile<5>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 6: process_tile<6>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 7: process_tile<7>(u, g, k0, nk, rows, fac, aux, tab); break;
-    default: process_tile<8>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 1: process_tile<1, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 2: process_tile<2, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 3: process_tile<3, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+    default:
+      if constexpr (MAXNL == 4) {
+        process_tile<4, CAP>(u, g, k0, nk, rows, fac, aux, tab);
+      } else {
+        switch (g.n_layers) {
+          case 4: process_tile<4, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 5: process_tile<5, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 6: process_tile<6, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 7: process_tile<7, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+          default: process_tile<8, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+        }
+      }
+      break;
   }
 }
 
@@ -572,9 +603,10 @@ __global__ void batch_reset_kernel(BatchHdr* __restrict__ hdr) {
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) batch_kernel(
     char* __restrict__ plan) {
-  __shared__ __align__(16) float2 lds[kBatchLds];
-  __shared__ float2 fac[kBatchFactSc * kBatchFactNP];
-  __shared__ float aux[kBatchFactSc * (2 * kBatchMaxLayers + 1)];
+  using CAP = TileCap<8>;
+  __shared__ __align__(16) float2 lds[CAP::rows];
+  __shared__ float2 fac[CAP::fac];
+  __shared__ float aux[CAP::fsc * CAP::aux];
   __shared__ SymTab tab;
   __shared__ int s_item;
   BatchHdr* hdr = reinterpret_cast<BatchHdr*>(plan);
@@ -590,20 +622,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     const BatchItem item = items[it];
     const BatchUe& u = ues[item.ue];
     const Geom& g = u.g;  // read in place (a private copy indexed at run time would spill)
-    process_any(u, g, item.k0, item.nk, lds, fac, aux, tab);
+    process_any<8>(u, g, item.k0, item.nk, lds, fac, aux, tab);
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
-// The whole chain for a batch of slots of one shape (up to 8 layers) in one launch: block
+// The whole chain for a batch of slots of one shape (up to MAXNL layers) in one launch: block
 // (slot, tile of nk subcarriers) stages the tile's pilot estimates and detects and demaps its
-// resource elements, as a work item of the multi-UE launch does.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
-receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
-               const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
-  __shared__ __align__(16) float2 lds[kBatchLds];
-  __shared__ float2 fac[kBatchFactSc * kBatchFactNP];
-  __shared__ float aux[kBatchFactSc * (2 * kBatchMaxLayers + 1)];
+// resource elements, as a work item of the multi-UE launch does.  The 4-layer form holds 4
+// blocks per CU (LDS and registers), the 8-layer form 3.
+template <int MAXNL>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(MAXNL == 4 ? 4 : 3, 8)))
+    receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
+                   const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
+  using CAP = TileCap<MAXNL>;
+  __shared__ __align__(16) float2 lds[CAP::rows];
+  __shared__ float2 fac[CAP::fac];
+  __shared__ float aux[CAP::fsc * CAP::aux];
   __shared__ SymTab tab;
   const int ntiles = (g.n_sc + nk - 1) / nk;
   const int slot = blockIdx.x / ntiles;
@@ -615,23 +651,35 @@ receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__
   u.nv = nvar + slot;
   u.llr = llr + (int64_t)slot * g.n_dsym * g.n_sc * g.n_layers * g.qm;
   const int n = min(nk, g.n_sc - k0);
-  process_any(u, g, k0, n, lds, fac, aux, tab);
+  process_any<MAXNL>(u, g, k0, n, lds, fac, aux, tab);
 }
 
 }  // namespace
 
-// Tile width of the one-launch chain: about tile_re resource elements, at most kBatchFactSc
+namespace {
+struct CapRT {
+  int rows, fac, fsc;
+};
+CapRT receive_cap(const Geom& g) {
+  if (g.n_layers <= 4) return {TileCap<4>::rows, TileCap<4>::fac, TileCap<4>::fsc};
+  return {TileCap<8>::rows, TileCap<8>::fac, TileCap<8>::fsc};
+}
+}  // namespace
+
+// Tile width of the one-launch chain: about tile_re resource elements, at most fsc
 // subcarriers; with two occasions and at most 4 layers the widest (not under 8 subcarriers)
 // whose channel pairs fit the block's LDS at every tile, else pilot rows that fit.
 int receive_tile(const Geom& g, int tile_re) {
+  const CapRT cap = receive_cap(g);
   int want = tile_re / g.n_dsym;
-  want = want < 1 ? 1 : (want > kBatchFactSc ? kBatchFactSc : want);
+  want = want < 1 ? 1 : (want > cap.fsc ? cap.fsc : want);
   const int per = batch_row_stride(g.n_rx, g.n_layers);
   auto all_fit = [&](int nk, bool pair) {
     for (int k0 = 0; k0 < g.n_sc; k0 += nk) {
       const int n = g.n_sc - k0 < nk ? g.n_sc - k0 : nk;
       const int rows = batch_tile_rows(g, k0, n);
-      if (pair ? !batch_pair_fits(g, rows, n) : rows * per > kBatchLds) return false;
+      if (pair ? !batch_pair_fits(g, rows, n, cap.rows, cap.fac) : rows * per > cap.rows)
+        return false;
     }
     return true;
   };
@@ -647,8 +695,11 @@ int receive_tile(const Geom& g, int tile_re) {
 hipError_t launch_receive(const Geom& g, const float2* rx, const float2* pil, const float* nvar,
                           float* llr, int nk, hipStream_t s) {
   const int64_t ntiles = (g.n_sc + nk - 1) / nk;
-  hipLaunchKernelGGL(receive_kernel, dim3((unsigned)(g.n_slots * ntiles)), dim3(256), 0, s, g,
-                     rx, pil, nvar, llr, nk);
+  const dim3 grid((unsigned)(g.n_slots * ntiles));
+  if (g.n_layers <= 4)
+    hipLaunchKernelGGL(receive_kernel<4>, grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+  else
+    hipLaunchKernelGGL(receive_kernel<8>, grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
   return hipGetLastError();
 }
 

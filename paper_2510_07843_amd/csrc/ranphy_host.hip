@@ -359,9 +359,9 @@ static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<
       // two occasions, up to 4 layers: the widest tile (not under 8 subcarriers) whose
       // channel pairs fit; otherwise pilot rows that fit
       int np = nk;
-      while (np >= 8 && !ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np))
+      while (np >= 8 && !ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np, ranphy::TileCap<8>::rows, ranphy::TileCap<8>::fac))
         np = (np + 1) / 2;
-      if (np >= 8 && ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np)) nk = np;
+      if (np >= 8 && ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np, ranphy::TileCap<8>::rows, ranphy::TileCap<8>::fac)) nk = np;
       while (nk > 1 && ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) nk = (nk + 1) / 2;
       if (ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) return RANPHY_ERR_UNSUPPORTED;
       // class: layers, modulation, antennas

@@ -14,7 +14,8 @@ from typing import Dict, Optional, Sequence
 import numpy as np
 import torch
 
-from . import (cnn_adam, cnn_forward, cnn_grad, cnn_param_count, cnn_workspace_bytes)
+from . import (chest_ls, cnn_adam, cnn_denoise, cnn_forward, cnn_grad, cnn_param_count,
+               cnn_workspace_bytes, mmse_detect)
 
 CHANNELS = (2, 32, 32, 32, 2)
 LAYER_PARAMS = 9 * 32 * 32 + 32
@@ -104,3 +105,41 @@ def choose_gate(params: torch.Tensor, h_est: torch.Tensor, h_true: torch.Tensor,
     return dict(min_noise_var=min_nv, max_snr_db=top,
                 nmse=[dict(snr_db=s, plain_db=round(a, 3), refined_db=round(b, 3),
                            gain_db=round(a - b, 3)) for s, a, b in table])
+
+
+def sinr_db(x_hat: np.ndarray, x: np.ndarray) -> float:
+    """Post-equalisation SINR E|x|^2 / E|x_hat - x|^2 in dB."""
+    return 10.0 * math.log10(float(np.mean(np.abs(x) ** 2)) /
+                             float(np.mean(np.abs(x_hat - x) ** 2)))
+
+
+def choose_gate_sinr(params: torch.Tensor, shape, rx: torch.Tensor, pilots: torch.Tensor,
+                     noise_var: torch.Tensor, x_true: np.ndarray, snr_db: Sequence[float]) -> Dict:
+    """The noise-variance gate judged on what detection sees: per SNR point of full validation
+    slots, the post-equalisation SINR of the FP32 detector with the plain and with the refined
+    (ungated) estimate against the transmitted symbols; refine up to the highest SNR point at
+    or below which every point gains, keep the plain estimate above it."""
+    h = chest_ls(shape, rx, pilots)
+    hr = cnn_denoise(shape, params, h, noise_var=noise_var)
+    xs = {}
+    for name, est in (("plain", h), ("refined", hr)):
+        x, _ = mmse_detect(shape, rx, est, noise_var)
+        torch.cuda.synchronize()
+        xs[name] = x.cpu().numpy().reshape(x_true.shape)
+    snr = np.asarray(snr_db, dtype=float)
+    table = []
+    for s in sorted(set(snr.tolist())):
+        sel = np.flatnonzero(snr == s)
+        a = sinr_db(xs["plain"][sel], x_true[sel])
+        b = sinr_db(xs["refined"][sel], x_true[sel])
+        table.append((s, a, b))
+    top = None
+    for s, a, b in table:
+        if b - a > 0.0:
+            top = s
+        else:
+            break
+    min_nv = math.inf if top is None else 10.0 ** (-top / 10.0)
+    return dict(min_noise_var=min_nv, max_snr_db=top,
+                sinr=[dict(snr_db=s, plain_db=round(a, 3), refined_db=round(b, 3),
+                           gain_db=round(b - a, 3)) for s, a, b in table])
