@@ -44,20 +44,27 @@ __host__ __device__ inline int batch_row_stride(int nr, int nl) { return (nr * n
 __host__ __device__ inline int batch_pair_stride(int nr, int nl) { return nr * nl + 1; }
 __host__ __device__ inline int batch_gram_stride(int nl) { return (3 * nl * (nl + 1) / 2) | 1; }
 __host__ __device__ inline int batch_pair_base(int rows, int rs) { return (rows * rs + 1) & ~1; }
-// LDS capacities of a block serving up to MAXNL layers: complex values of pilot rows and
-// channel pairs (rows), complex values of factors or Gram pieces (fac), the factor and aux
-// strides per subcarrier, and the subcarriers of a one-occasion tile (fsc).  The 4-layer form
-// fits 4 blocks per CU; the 8-layer form 3.
-template <int MAXNL>
+// LDS capacities of a block serving up to MAXNL layers with BLOCKS blocks per CU: complex
+// values of pilot rows and channel pairs (rows), complex values of factors or Gram pieces
+// (fac), the factor and aux strides per subcarrier, and the subcarriers of a one-occasion
+// tile (fsc).  A CU has 160 KB of LDS.
+template <int MAXNL, int BLOCKS>
 struct TileCap;
 template <>
-struct TileCap<8> {
+struct TileCap<8, 3> {
   static constexpr int rows = kBatchLds, fac = kBatchFactSc * kBatchFactNP, fnp = kBatchFactNP,
                        aux = 2 * 8 + 1, fsc = kBatchFactSc;
+  static constexpr bool one_occ = false;
 };
 template <>
-struct TileCap<4> {
+struct TileCap<4, 4> {  // two-occasion tiles of 16 x 4 fit 21 subcarriers
   static constexpr int rows = 3776, fac = 1024, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
+  static constexpr bool one_occ = false;
+};
+template <>
+struct TileCap<4, 5> {  // one-occasion tiles only
+  static constexpr int rows = 2944, fac = 640, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
+  static constexpr bool one_occ = true;
 };
 
 __host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk, int cap_rows,

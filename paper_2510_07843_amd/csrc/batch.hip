@@ -557,7 +557,7 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
                                              SymTab& tab) {
   int jlo, nj;
   stage_pilots(u, g, k0, nk, rows, tab, jlo, nj);
-  if (g.n_occ == 1) {
+  if (CAP::one_occ || g.n_occ == 1) {  // a one-occasion form is launched for those only
     factor_tile<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux);
     detect_tile_fact<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux, tab);
     return;
@@ -573,10 +573,10 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
   detect_tile<NL>(u, g, k0, nk, jlo, nj, rows, tab);
 }
 
-template <int MAXNL>
+template <int MAXNL, int BLOCKS>
 __device__ __forceinline__ void process_any(const BatchUe& u, const Geom& g, int k0, int nk,
                                             float2* rows, float2* fac, float* aux, SymTab& tab) {
-  using CAP = TileCap<MAXNL>;
+  using CAP = TileCap<MAXNL, BLOCKS>;
   switch (g.n_layers) {  // uniform over the block
     case 1: process_tile<1, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
     case 2: process_tile<2, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
@@ -603,7 +603,7 @@ __global__ void batch_reset_kernel(BatchHdr* __restrict__ hdr) {
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) batch_kernel(
     char* __restrict__ plan) {
-  using CAP = TileCap<8>;
+  using CAP = TileCap<8, 3>;
   __shared__ __align__(16) float2 lds[CAP::rows];
   __shared__ float2 fac[CAP::fac];
   __shared__ float aux[CAP::fsc * CAP::aux];
@@ -622,21 +622,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     const BatchItem item = items[it];
     const BatchUe& u = ues[item.ue];
     const Geom& g = u.g;  // read in place (a private copy indexed at run time would spill)
-    process_any<8>(u, g, item.k0, item.nk, lds, fac, aux, tab);
+    process_any<8, 3>(u, g, item.k0, item.nk, lds, fac, aux, tab);
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
 // The whole chain for a batch of slots of one shape (up to MAXNL layers) in one launch: block
 // (slot, tile of nk subcarriers) stages the tile's pilot estimates and detects and demaps its
-// resource elements, as a work item of the multi-UE launch does.  The 4-layer form holds 4
-// blocks per CU (LDS and registers), the 8-layer form 3.
-template <int MAXNL>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(MAXNL == 4 ? 4 : 3, 8)))
-    receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
-                   const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
-  using CAP = TileCap<MAXNL>;
+// resource elements, as a work item of the multi-UE launch does.  BLOCKS blocks fit a CU
+// (LDS and registers).
+template <int MAXNL, int BLOCKS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BLOCKS, 8)))
+receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
+               const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
+  using CAP = TileCap<MAXNL, BLOCKS>;
   __shared__ __align__(16) float2 lds[CAP::rows];
   __shared__ float2 fac[CAP::fac];
   __shared__ float aux[CAP::fsc * CAP::aux];
@@ -651,7 +650,7 @@ __global__ void __launch_bounds__(256)
   u.nv = nvar + slot;
   u.llr = llr + (int64_t)slot * g.n_dsym * g.n_sc * g.n_layers * g.qm;
   const int n = min(nk, g.n_sc - k0);
-  process_any<MAXNL>(u, g, k0, n, lds, fac, aux, tab);
+  process_any<MAXNL, BLOCKS>(u, g, k0, n, lds, fac, aux, tab);
 }
 
 }  // namespace
@@ -660,9 +659,19 @@ namespace {
 struct CapRT {
   int rows, fac, fsc;
 };
+// The kernel form for a shape: up to 4 layers 5 blocks per CU (one occasion) or 4 (several:
+// the channel pairs need the room), else the 8-layer form at 3.
+int receive_form(const Geom& g) { return g.n_layers > 4 ? 0 : (g.n_occ == 1 ? 2 : 1); }
+template <class CAP>
+CapRT cap_rt() {
+  return {CAP::rows, CAP::fac, CAP::fsc};
+}
 CapRT receive_cap(const Geom& g) {
-  if (g.n_layers <= 4) return {TileCap<4>::rows, TileCap<4>::fac, TileCap<4>::fsc};
-  return {TileCap<8>::rows, TileCap<8>::fac, TileCap<8>::fsc};
+  switch (receive_form(g)) {
+    case 2: return cap_rt<TileCap<4, 5>>();
+    case 1: return cap_rt<TileCap<4, 4>>();
+    default: return cap_rt<TileCap<8, 3>>();
+  }
 }
 }  // namespace
 
@@ -696,10 +705,17 @@ hipError_t launch_receive(const Geom& g, const float2* rx, const float2* pil, co
                           float* llr, int nk, hipStream_t s) {
   const int64_t ntiles = (g.n_sc + nk - 1) / nk;
   const dim3 grid((unsigned)(g.n_slots * ntiles));
-  if (g.n_layers <= 4)
-    hipLaunchKernelGGL(receive_kernel<4>, grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
-  else
-    hipLaunchKernelGGL(receive_kernel<8>, grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+  switch (receive_form(g)) {
+    case 2:
+      hipLaunchKernelGGL((receive_kernel<4, 5>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+      break;
+    case 1:
+      hipLaunchKernelGGL((receive_kernel<4, 4>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+      break;
+    default:
+      hipLaunchKernelGGL((receive_kernel<8, 3>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -359,9 +359,12 @@ static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<
       // two occasions, up to 4 layers: the widest tile (not under 8 subcarriers) whose
       // channel pairs fit; otherwise pilot rows that fit
       int np = nk;
-      while (np >= 8 && !ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np, ranphy::TileCap<8>::rows, ranphy::TileCap<8>::fac))
-        np = (np + 1) / 2;
-      if (np >= 8 && ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, np), np, ranphy::TileCap<8>::rows, ranphy::TileCap<8>::fac)) nk = np;
+      using Cap = ranphy::TileCap<8, 3>;
+      auto fits = [&](int n) {
+        return ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, n), n, Cap::rows, Cap::fac);
+      };
+      while (np >= 8 && !fits(np)) np = (np + 1) / 2;
+      if (np >= 8 && fits(np)) nk = np;
       while (nk > 1 && ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) nk = (nk + 1) / 2;
       if (ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) return RANPHY_ERR_UNSUPPORTED;
       // class: layers, modulation, antennas
