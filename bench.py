@@ -335,7 +335,11 @@ def bench_batch(args, torch, ranphy, synth):
     ues = make_batch_ues(torch, synth, n_ue=args.slots or 200)
     t_gen = time.perf_counter() - t0
     re = sum(u["shape"].n_dsym * u["shape"].n_sc for u in ues)
-    tuned = tune.autotune(ues, reps=3)
+    if args.batch_config:  # a fixed configuration (profiled runs): no autotuning launches
+        tile, bpc = (int(v) for v in args.batch_config.split(","))
+        tuned = tune.autotune(ues, tiles=(tile,), blocks_per_cu=(bpc,), reps=1)
+    else:
+        tuned = tune.autotune(ues, reps=3)
     b, nb = tuned["batch"], tuned["n_blocks"]
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -382,6 +386,20 @@ def bench_batch(args, torch, ranphy, synth):
     e1.record()
     torch.cuda.synchronize()
     ms_per_ue = e0.elapsed_time(e1) / max(1, args.steps // 4)
+
+    def per_ue_receive():  # the one-launch chain, one launch per UE
+        for u in ues:
+            ranphy.receive(u["shape"], u["rx"], u["pilots"], u["noise_var"], llr=u["llr"])
+
+    for _ in range(2):
+        per_ue_receive()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(max(1, args.steps // 4)):
+        per_ue_receive()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_ue_rx = e0.elapsed_time(e1) / max(1, args.steps // 4)
     # algorithmic bytes and flops of the fused chain: every input read once, LLRs written once
     nbytes = flops = 0
     for u in ues:
@@ -417,7 +435,10 @@ def bench_batch(args, torch, ranphy, synth):
         "roofline": roof,
         "autotune": tuned["table"],
         "variants": {"per_ue_launches": {"value": re / (ms_per_ue * 1e-3), "ms_per_step": ms_per_ue,
-                                         "launches_per_step": 3 * len(ues)}},
+                                         "launches_per_step": 3 * len(ues)},
+                     "per_ue_receive": {"value": re / (ms_per_ue_rx * 1e-3),
+                                        "ms_per_step": ms_per_ue_rx,
+                                        "launches_per_step": len(ues)}},
     }
     if not args.no_cpu_baseline:
         import oracle
@@ -449,6 +470,8 @@ def main():
                          "square 2x2/4x4/8x8 at 60 RB, 15 kHz; batch: 200 UEs of uneven "
                          "allocations in one persistent launch (--slots sets the UE count)")
     ap.add_argument("--slots", type=int, default=None, help="override the batch size")
+    ap.add_argument("--batch-config", default=None, metavar="TILE_RE,BLOCKS_PER_CU",
+                    help="batch workload: use this plan configuration instead of autotuning")
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="input precision of the detector's Gram and matched filter")
