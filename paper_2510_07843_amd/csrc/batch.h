@@ -55,16 +55,19 @@ struct TileCap<8, 3> {
   static constexpr int rows = kBatchLds, fac = kBatchFactSc * kBatchFactNP, fnp = kBatchFactNP,
                        aux = 2 * 8 + 1, fsc = kBatchFactSc;
   static constexpr bool one_occ = false;
+  static constexpr int stage_batch = 4;  // pilot estimates per thread whose loads are in flight together
 };
 template <>
 struct TileCap<4, 4> {  // two-occasion tiles of 16 x 4 fit 21 subcarriers
   static constexpr int rows = 3776, fac = 1024, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
   static constexpr bool one_occ = false;
+  static constexpr int stage_batch = 4;
 };
 template <>
 struct TileCap<4, 5> {  // one-occasion tiles only
   static constexpr int rows = 2944, fac = 640, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
   static constexpr bool one_occ = true;
+  static constexpr int stage_batch = 1;  // within the 5-block register budget
 };
 
 __host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk, int cap_rows,

@@ -1,29 +1,35 @@
-// Many UEs of uneven allocations in one persistent launch: LS estimation, interpolation,
-// LMMSE detection and max-log demapping for every UE of a batch.  The paper names divergence
-// and scheduling overhead as the weak points of SIMT processing for PHY work (Sec. V); here
-// the launch does not depend on the batch's composition and the work is dealt out in
-// homogeneous pieces.
-//
-// A plan (built on the host, resident in device memory) holds one record per UE (its
-// geometry and buffers) and a list of work items, each a tile of consecutive subcarriers of
-// one UE, sorted so that items of one class (layers, modulation, antennas) are adjacent and
-// the heaviest come first.  Every block of the persistent grid takes the next item from an
-// atomic counter until the list is exhausted, so the grid is as large as the chip holds and
-// no more; a one-thread kernel clears the counter before each run (both capture into a HIP
-// graph).  An item is processed by one block without depending on any other:
+// Tiles of the whole receive chain -- LS estimation, interpolation, LMMSE detection and
+// max-log demapping -- each processed by one block without depending on any other, and the
+// two launches built from them:
+//   * receive_kernel (ranphy_receive): one launch over the slots of one shape, block = (slot,
+//     tile of consecutive subcarriers), in three compiled forms by layer count and DMRS
+//     occasions (the LDS and registers each needs set how many blocks share a CU);
+//   * batch_kernel (ranphy_batch_*): many UEs of uneven allocations in one persistent
+//     launch.  The paper names divergence and scheduling overhead as the weak points of SIMT
+//     processing (Sec. V); here the launch does not depend on the batch's composition and the
+//     work is dealt out in homogeneous pieces.  A plan (built on the host, resident in device
+//     memory) holds one record per UE (its geometry and buffers) and a list of work items,
+//     each a tile of one UE, sorted so that items of one class (layers, modulation, antennas)
+//     are adjacent and the heaviest come first.  Every block of the persistent grid takes the
+//     next item from an atomic counter until the list is exhausted; a one-thread kernel
+//     clears the counter before each run (both capture into a HIP graph).
+// A tile is processed as
 //   1. the LS estimate (Sec. III-B: channel estimation) of every pilot the tile's
-//      subcarriers interpolate from, per occasion, into LDS;
-//   2. with one DMRS occasion (the channel held over the slot): each subcarrier's Gram
+//      subcarriers interpolate from, per occasion, into LDS, with the per-symbol tables;
+//   2. one DMRS occasion (the channel held over the slot): each subcarrier's Gram
 //      G = H^H H + s2 I, one (subcarrier, entry) per thread, then its Cholesky factor
-//      (Sec. IV, Fig. 4), reciprocal diagonal and d = diag(G^-1), one subcarrier per
-//      thread, staged in LDS; per resource element (all data symbols) the matched filter
-//      streamed over the receive antennas, forward / backward substitution with the staged
-//      factor, unbiasing, and the max-log LLRs written to the UE's output;
-//   2'. with several occasions (a time-varying estimate): per resource element the
-//      interpolation in frequency and time, Gram and matched filter, factorisation,
-//      substitution, unbiasing and LLRs.
-// Layers 1..8 (a template parameter: one branch per item, uniform over the block),
-// antennas 1..64, every modulation and DMRS configuration of the library.
+//      (Sec. IV, Fig. 4), reciprocal diagonal and d = diag(G^-1), one subcarrier per thread,
+//      staged in LDS; per resource element the matched filter streamed over the receive
+//      antennas, forward / backward substitution with the staged factor, unbiasing, and the
+//      max-log LLRs written to the output;
+//   2'. two occasions, up to 4 layers: per subcarrier the channel pair (H0, H1 - H0) and the
+//      three Gram pieces whose blend is the Gram at any time weight; per resource element the
+//      blended Gram, its factorisation, the matched filter from the staged pairs,
+//      substitution, unbiasing and LLRs;
+//   2''. otherwise: per resource element the interpolation in frequency and time, Gram and
+//      matched filter, factorisation, substitution, unbiasing and LLRs.
+// Layers 1..8 (a template parameter: one branch per tile, uniform over the block), antennas
+// 1..64, every modulation and DMRS configuration of the library.
 #include <float.h>
 
 #include "batch.h"
@@ -497,13 +503,65 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
   }
 }
 
+// The LS estimates of the tile's pilot rows, every occasion: each thread's estimates are
+// taken kStageBatch at a time with every load issued before the first is used (one memory
+// round trip per batch instead of one per estimate); indices are clamped into range and the
+// surplus discarded, so the loads need no branches.  T (the time cover length) is a template
+// parameter so that its loop unrolls.
+template <int T, int kStageBatch>
+__device__ __forceinline__ void stage_rows(const BatchUe& u, const Geom& g, int jlo, int nj,
+                                           float2* __restrict__ rows) {
+  const int C = g.comb, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot, NSC = g.n_sc;
+  const int per_occ = nj * NR * NL, total = g.n_occ * per_occ, RS = batch_row_stride(NR, NL);
+  const int s00 = g.sym0[0], s01 = g.sym0[1], s02 = g.sym0[2], s03 = g.sym0[3];
+  const FastDiv by_nl(NL), by_nr(NR), by_occ(per_occ);
+  constexpr float inv_t = 1.f / (float)T;
+  for (int f0 = threadIdx.x; f0 < total; f0 += kStageBatch * blockDim.x) {
+    float2 yv[kStageBatch][T], qv[kStageBatch][T];
+    int dst[kStageBatch];
+    bool in_band[kStageBatch];
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      const int f = min(f0 + b * (int)blockDim.x, total - 1);
+      const int o = by_occ(f);
+      const int fo = f - o * per_occ;
+      const int fl = by_nl(fo);
+      const int p = fo - fl * NL;
+      const int jj = by_nr(fl);
+      const int r = fl - jj * NR;
+      const int j = jlo + jj;
+      const int k = C * j + (p & (C - 1));
+      const int s0 = o == 0 ? s00 : (o == 1 ? s01 : (o == 2 ? s02 : s03));
+      const int kc = min(k, NSC - 1);
+      in_band[b] = k < NSC;
+      dst[b] = (o * nj + jj) * RS + r * NL + p;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        yv[b][t] = u.rx[((int64_t)(s0 + t) * NSC + kc) * NR + r];
+        qv[b][t] = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kStageBatch; ++b) {
+      if (f0 + b * (int)blockDim.x < total) {
+        float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int t = 0; t < T; ++t) cmac_c(acc, qv[b][t], yv[b][t]);  // y conj(q)
+        if (!in_band[b]) acc = make_float2(0.f, 0.f);
+        rows[dst[b]] = make_float2(acc.x * inv_t, acc.y * inv_t);
+      }
+    }
+  }
+}
+
 // The LS estimate (Sec. III-B) of every pilot the tile k0 .. k0 + nk - 1 interpolates from,
 // every occasion, into rows[o][j - jlo][r][p] (rows of batch_row_stride values), and the
 // symbol tables into tab; returns jlo and the pilot count nj.  Ends with a barrier.
+template <int SB>
 __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, int k0, int nk,
                                              float2* __restrict__ rows, SymTab& tab, int& jlo,
                                              int& nj) {
-  const int C = g.comb, T = g.td, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot;
+  const int T = g.td, NL = g.n_layers, J = g.n_pilot;
   // pilot range of the tile: a port's pilot indices do not decrease with the subcarrier
   int lo = J, hi = 0;
   for (int p = 0; p < NL; ++p) {
@@ -516,30 +574,10 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
   }
   jlo = lo;
   nj = hi - lo + 1;
-  const int per_occ = nj * NR * NL, RS = batch_row_stride(NR, NL);
-  const float inv_t = 1.f / (float)T;
-  const FastDiv by_nl(NL), by_nr(NR);
-  for (int o = 0; o < g.n_occ; ++o) {  // uniform: the occasion's symbol is a scalar load
-    const float2* __restrict__ rx0 = u.rx + (int64_t)g.sym0[o] * g.n_sc * NR;
-#pragma unroll 4
-    for (int f = threadIdx.x; f < per_occ; f += blockDim.x) {
-      const int fl = by_nl(f);
-      const int p = f - fl * NL;
-      const int jj = by_nr(fl);
-      const int r = fl - jj * NR;
-      const int j = jlo + jj;
-      const int k = C * j + (p & (C - 1));
-      float2 acc = make_float2(0.f, 0.f);
-      if (k < g.n_sc) {
-        for (int t = 0; t < T; ++t) {
-          const float2 y = rx0[((int64_t)t * g.n_sc + k) * NR + r];
-          const float2 q = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
-          cmac_c(acc, q, y);  // y conj(q)
-        }
-      }
-      rows[(o * nj + jj) * RS + r * NL + p] = make_float2(acc.x * inv_t, acc.y * inv_t);
-    }
-  }
+  if (T == 1)
+    stage_rows<1, SB>(u, g, jlo, nj, rows);
+  else
+    stage_rows<2, SB>(u, g, jlo, nj, rows);
   if (threadIdx.x < g.n_dsym) {
     const int d = threadIdx.x;
     tab.dsym[d] = g.dsym[d];
@@ -556,7 +594,7 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
                                              float2* rows, float2* fac, float* aux,
                                              SymTab& tab) {
   int jlo, nj;
-  stage_pilots(u, g, k0, nk, rows, tab, jlo, nj);
+  stage_pilots<CAP::stage_batch>(u, g, k0, nk, rows, tab, jlo, nj);
   if (CAP::one_occ || g.n_occ == 1) {  // a one-occasion form is launched for those only
     factor_tile<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux);
     detect_tile_fact<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux, tab);
