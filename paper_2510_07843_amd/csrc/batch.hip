@@ -318,7 +318,7 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
     const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
     const float4* q = pair + kk * PS;
-#pragma unroll 8
+#pragma unroll 16
     for (int r = 0; r < NR; ++r) {
       const float2 y = yrow[r];
 #pragma unroll
