@@ -128,6 +128,11 @@ SHAPES = {
     "prb2_l8_r64": SlotShape(2, 14, 64, 8, 8, 4, 2, (2,), 2),
     "prb9_l6_2occ_r40": SlotShape(9, 14, 40, 6, 4, 8, 1, (2, 10), 1),
     "prb1_l4_dmrs_end": SlotShape(1, 14, 32, 4, 6, 2, 2, (12,), 2),
+    # two occasions up to 4 layers: the per-subcarrier channel pairs and Gram pieces
+    "prb7_l3_r12_2occ": SlotShape(7, 14, 12, 3, 6, 4, 1, (1, 10), 2),
+    "prb3_l2_r64_2occ": SlotShape(3, 14, 64, 2, 4, 2, 1, (2, 11), 2),
+    "prb4_l4_short_2occ": SlotShape(4, 7, 8, 4, 2, 4, 1, (0, 5), 2),
+    "prb2_l1_r4_2occ_td2": SlotShape(2, 14, 4, 1, 8, 2, 2, (2, 10), 3),
     "p2": synth.CONFIGS["p2"]["shape"].with_slots(2),
     "p4": synth.CONFIGS["p4"]["shape"].with_slots(2),
     "p8": synth.CONFIGS["p8"]["shape"].with_slots(2),
