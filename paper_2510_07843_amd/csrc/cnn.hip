@@ -93,7 +93,8 @@ __global__ void cnn_input_kernel(const float* __restrict__ x, __bf16* __restrict
 // > 0) (input gradient: no bias); MODE 2, channels 0 and 1 to out_f[..][2], with y = conv + b
 // and r = 1 / sigma of the group (1 without noise variances): res + y / r (refinement), or
 // r res + y (training, normalised units, norm_out); groups with gate_nv < gate_min (or no
-// positive noise variance) keep res.
+// positive noise variance) keep res, and in MODE 0 (given noise variances only for
+// inference) such groups are skipped.
 template <int MODE>
 __global__ void __launch_bounds__(256) cnn_conv_kernel(Grid2 gd, const __bf16* __restrict__ in,
                                                        const __bf16* __restrict__ w,
@@ -123,6 +124,10 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(Grid2 gd, const __bf16* _
   // MODE 2: groups whose noise variance is below gate_min keep their input (out = res)
   const float r = inv_sigma(nv, grp);
   const bool keep = nv == nullptr || (nv[grp] >= gate_min && r > 0.f);
+  // Inference: a group that keeps its input needs no hidden activations (MODE 0 is given the
+  // noise variances only then) and no products in the last layer.
+  if (MODE == 0 && !keep) return;  // wave-uniform
+  const bool work = MODE != 2 || norm_out || keep;
 
   floatx4 acc[4][2];
 #pragma unroll
@@ -136,7 +141,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(Grid2 gd, const __bf16* _
     prow[pp] = (p0 + pp) / gd.cols;
     pcol[pp] = (p0 + pp) - prow[pp] * gd.cols;
   }
-  for (int t = 0; t < kCnnTaps; ++t) {
+  for (int t = 0; t < (work ? kCnnTaps : 0); ++t) {
     const int dy = t / 3 - 1, dx = t % 3 - 1;
     bool any = false;
 #pragma unroll
@@ -395,9 +400,10 @@ hipError_t forward(const Grid2& gd, const float* params, const float* x, float* 
                      x, w.act[0], nq, (int64_t)gd.npx * gd.nimg, nv);
   // training keeps a0 .. a3; inference ping-pongs between two buffers
   __bf16* a[4] = {w.act[0], w.act[1], keep ? w.act[2] : w.act[0], keep ? w.act[3] : w.act[1]};
-  for (int l = 0; l < 3; ++l) {
+  for (int l = 0; l < 3; ++l) {  // inference skips the groups the gate keeps plain
     const hipError_t e = conv<0>(gd, a[l], w.wf + l * kWsz, params + l * kCnnLayerParams + kWsz,
-                                 nullptr, a[l + 1], nullptr, nullptr, s);
+                                 nullptr, a[l + 1], nullptr, nullptr, s, keep ? nullptr : nv,
+                                 gate_min);
     if (e != hipSuccess) return e;
   }
   // training (keep) writes the output in normalised units for the loss
