@@ -77,6 +77,33 @@ __host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk,
   return base + 2 * nk * batch_pair_stride(g.n_rx, g.n_layers) <= cap_rows &&
          nk * batch_gram_stride(g.n_layers) <= cap_fac;
 }
+// One DMRS occasion: per subcarrier the tile may stage the unbiased filter W = diag(1/mu)
+// G^-1 H^H (Nl x Nr complex, odd stride) after the pilot rows, so that a resource element
+// needs only x = W y.  It fits when the rows and nk filters fit the rows area.
+__host__ __device__ inline int batch_w_stride(int nr, int nl) { return (nr * nl) | 1; }
+__host__ __device__ inline bool batch_w_fits(const Geom& g, int rows, int nk, int cap_rows) {
+  if (g.n_occ != 1) return false;
+  const int base = batch_pair_base(rows, batch_row_stride(g.n_rx, g.n_layers));
+  return base + nk * batch_w_stride(g.n_rx, g.n_layers) <= cap_rows;
+}
+// Pilot rows any tile of nk consecutive subcarriers can span (every occasion, every port).
+__host__ __device__ inline int batch_rows_bound(const Geom& g, int nk) {
+  return g.n_occ * ((nk - 1) / g.comb + 4);
+}
+// Whether a shape takes the pair (two occasions) or the filter (one occasion) path: decided by
+// the shape alone, so that the arithmetic of a resource element does not depend on the tile
+// width; a shape qualifies when any tile of 8 subcarriers fits, and the host then picks tile
+// widths that fit.
+__host__ __device__ inline bool batch_pair_path(const Geom& g, int cap_rows, int cap_fac) {
+  return batch_pair_fits(g, batch_rows_bound(g, 8), 8, cap_rows, cap_fac);
+}
+// The filter form pays where the per-element substitutions it removes are a large share of
+// the work and its filters leave the tiles wide: 3..8 layers, at most 64 antenna-layer pairs
+// (measured on the paper's square shapes and the multi-UE mix).
+__host__ __device__ inline bool batch_w_path(const Geom& g, int cap_rows) {
+  return g.n_layers >= 3 && g.n_rx * g.n_layers <= 64 &&
+         batch_w_fits(g, batch_rows_bound(g, 8), 8, cap_rows);
+}
 // Pilot rows (occasions x pilot indices) a tile of nk subcarriers starting at k0 reads.
 int batch_tile_rows(const Geom& g, int k0, int nk);
 hipError_t launch_batch(void* plan, int blocks, hipStream_t s);

@@ -588,6 +588,95 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
   __syncthreads();
 }
 
+// One occasion, filter form: per (subcarrier, antenna) item the column W[:, r] of
+// W = diag(1/mu) G^-1 H^H, i.e. the two substitutions with the staged factor applied to
+// conj(H[r][:]) and each layer scaled by 1/mu_l = 1 / (1 - s2 d_l), into wf[kk][r][l]; then
+// per resource element x~ = W y, the variance s2 d_l / mu_l from the staged d, and the LLRs.
+// Same quantities as detect_tile_fact, with the substitutions taken once per subcarrier and
+// antenna instead of once per resource element.
+template <int NL, class CAP>
+__device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, int k0, int nk,
+                                              int jlo, const float2* __restrict__ rows,
+                                              const float2* __restrict__ fac,
+                                              const float* __restrict__ aux,
+                                              float2* __restrict__ wf, const SymTab& tab) {
+  const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
+  const int WS = batch_w_stride(NR, NL);
+  const float s2 = *u.nv;
+  const FastDiv by_nr(NR);
+  for (int f = threadIdx.x; f < nk * NR; f += blockDim.x) {  // (subcarrier, antenna)
+    const int kk = by_nr(f);
+    const int r = f - kk * NR;
+    const int k = k0 + kk;
+    const float2* L = fac + kk * CAP::fnp;
+    const float* ax = aux + kk * CAP::aux;
+    float2 wv[NL], xh[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {  // L w = conj(h_r)
+      int j0, j1;
+      float a;
+      freq_rule(g, i, k, j0, j1, a);
+      const float2 h = row_interp(rows, RS, NL, j0 - jlo, j1 - jlo, a, r, i);
+      float2 acc = make_float2(h.x, -h.y);
+#pragma unroll
+      for (int kq = 0; kq < i; ++kq) cmsb(acc, L[tri(i, kq)], wv[kq]);
+      wv[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
+    }
+#pragma unroll
+    for (int i = NL - 1; i >= 0; --i) {  // L^H x = w
+      float2 acc = wv[i];
+#pragma unroll
+      for (int kq = i + 1; kq < NL; ++kq) cmsb_c(acc, L[tri(kq, i)], xh[kq]);
+      xh[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
+    }
+    float2* w = wf + kk * WS + r * NL;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const float im = __builtin_amdgcn_rcpf(1.f - s2 * ax[NL + l]);
+      w[l] = make_float2(xh[l].x * im, xh[l].y * im);
+    }
+  }
+  __syncthreads();
+  const FastDiv by_nk(nk);
+  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
+    const int d = by_nk(e);
+    const int kk = e - d * nk;
+    const int k = k0 + kk;
+    const float* ax = aux + kk * CAP::aux;
+    const bool ok = ax[2 * NL] != 0.f;
+    float2 x[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) x[i] = make_float2(0.f, 0.f);
+    const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
+    const float2* w = wf + kk * WS;
+#pragma unroll 8
+    for (int r = 0; r < NR; ++r) {
+      const float2 y = yrow[r];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {  // x_l += W[l][r] y_r
+        const float2 c = w[r * NL + l];
+        x[l].x = fmaf(c.x, y.x, x[l].x);
+        x[l].x = fmaf(-c.y, y.y, x[l].x);
+        x[l].y = fmaf(c.x, y.y, x[l].y);
+        x[l].y = fmaf(c.y, y.x, x[l].y);
+      }
+    }
+    float* __restrict__ dst = u.llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const float sd = s2 * ax[NL + l];
+      const float vo = ok ? sd * __builtin_amdgcn_rcpf(1.f - sd) : __builtin_inff();
+      const float2 xo = ok ? x[l] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+      switch (g.qm) {
+        case 2: demap_store<2>(dst + l * 2, xo, vo); break;
+        case 4: demap_store<4>(dst + l * 4, xo, vo); break;
+        case 6: demap_store<6>(dst + l * 6, xo, vo); break;
+        default: demap_store<8>(dst + l * 8, xo, vo); break;
+      }
+    }
+  }
+}
+
 // One tile of nk subcarriers starting at k0: pilots staged, then the path for the DMRS layout.
 template <int NL, class CAP>
 __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk,
@@ -597,11 +686,16 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
   stage_pilots<CAP::stage_batch>(u, g, k0, nk, rows, tab, jlo, nj);
   if (CAP::one_occ || g.n_occ == 1) {  // a one-occasion form is launched for those only
     factor_tile<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux);
-    detect_tile_fact<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux, tab);
+    const int rs = batch_row_stride(g.n_rx, NL);
+    if (batch_w_path(g, CAP::rows))  // the host's tile widths fit for such shapes
+      detect_tile_w<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux,
+                             rows + batch_pair_base(g.n_occ * nj, rs), tab);
+    else
+      detect_tile_fact<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux, tab);
     return;
   }
   if constexpr (NL <= 4) {
-    if (batch_pair_fits(g, g.n_occ * nj, nk, CAP::rows, CAP::fac)) {
+    if (batch_pair_path(g, CAP::rows, CAP::fac)) {  // the host's tile widths fit
       float4* pair = reinterpret_cast<float4*>(
           rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
       detect_tile_pair<NL>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
@@ -714,29 +808,26 @@ CapRT receive_cap(const Geom& g) {
 }  // namespace
 
 // Tile width of the one-launch chain: about tile_re resource elements, at most fsc
-// subcarriers; with two occasions and at most 4 layers the widest (not under 8 subcarriers)
-// whose channel pairs fit the block's LDS at every tile, else pilot rows that fit.
+// subcarriers, and the widest below that whose staged data (channel pairs, filters or pilot
+// rows, by the shape's path) fit the block's LDS at every tile; 0 if none does.
 int receive_tile(const Geom& g, int tile_re) {
   const CapRT cap = receive_cap(g);
   int want = tile_re / g.n_dsym;
   want = want < 1 ? 1 : (want > cap.fsc ? cap.fsc : want);
   const int per = batch_row_stride(g.n_rx, g.n_layers);
-  auto all_fit = [&](int nk, bool pair) {
-    for (int k0 = 0; k0 < g.n_sc; k0 += nk) {
+  const bool pair = g.n_occ == 2 && batch_pair_path(g, cap.rows, cap.fac);
+  const bool wpath = g.n_occ == 1 && batch_w_path(g, cap.rows);
+  for (int nk = want; nk >= 1; --nk) {
+    bool ok = true;
+    for (int k0 = 0; k0 < g.n_sc && ok; k0 += nk) {
       const int n = g.n_sc - k0 < nk ? g.n_sc - k0 : nk;
       const int rows = batch_tile_rows(g, k0, n);
-      if (pair ? !batch_pair_fits(g, rows, n, cap.rows, cap.fac) : rows * per > cap.rows)
-        return false;
+      ok = pair ? batch_pair_fits(g, rows, n, cap.rows, cap.fac)
+                : (wpath ? batch_w_fits(g, rows, n, cap.rows) : rows * per <= cap.rows);
     }
-    return true;
-  };
-  if (g.n_occ == 2 && g.n_layers <= 4)
-    for (int nk = want; nk >= 8; nk = (nk + 1) / 2)
-      if (all_fit(nk, true)) return nk;
-  for (int nk = want;; nk = (nk + 1) / 2) {
-    if (all_fit(nk, false)) return nk;
-    if (nk == 1) return 0;
+    if (ok) return nk;
   }
+  return 0;
 }
 
 hipError_t launch_receive(const Geom& g, const float2* rx, const float2* pil, const float* nvar,

@@ -355,18 +355,20 @@ static int batch_build(const ranphy_ue* ues, int n_ue, int tile_re, std::vector<
     int want = std::max(1, tile_re / g.n_dsym);
     if (g.n_occ == 1) want = std::min(want, ranphy::kBatchFactSc);
     for (int k0 = 0; k0 < g.n_sc;) {
-      int nk = std::min(want, g.n_sc - k0);
-      // two occasions, up to 4 layers: the widest tile (not under 8 subcarriers) whose
-      // channel pairs fit; otherwise pilot rows that fit
-      int np = nk;
+      // the widest tile up to want whose staged data fit, by the shape's path (pair,
+      // filter, or pilot rows only); decided per shape, so the arithmetic of a resource
+      // element does not depend on tile_re
       using Cap = ranphy::TileCap<8, 3>;
-      auto fits = [&](int n) {
-        return ranphy::batch_pair_fits(g, ranphy::batch_tile_rows(g, k0, n), n, Cap::rows, Cap::fac);
-      };
-      while (np >= 8 && !fits(np)) np = (np + 1) / 2;
-      if (np >= 8 && fits(np)) nk = np;
-      while (nk > 1 && ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) nk = (nk + 1) / 2;
-      if (ranphy::batch_tile_rows(g, k0, nk) * per > ranphy::kBatchLds) return RANPHY_ERR_UNSUPPORTED;
+      const bool pair = g.n_occ == 2 && ranphy::batch_pair_path(g, Cap::rows, Cap::fac);
+      const bool wpath = g.n_occ == 1 && ranphy::batch_w_path(g, Cap::rows);
+      int nk = std::min(want, g.n_sc - k0);
+      for (; nk >= 1; --nk) {
+        const int rows = ranphy::batch_tile_rows(g, k0, nk);
+        if (pair ? ranphy::batch_pair_fits(g, rows, nk, Cap::rows, Cap::fac)
+                 : (wpath ? ranphy::batch_w_fits(g, rows, nk, Cap::rows) : rows * per <= Cap::rows))
+          break;
+      }
+      if (nk < 1) return RANPHY_ERR_UNSUPPORTED;
       // class: layers, modulation, antennas
       items.push_back({u, k0, nk, (g.n_layers * 16 + g.qm) * 128 + g.n_rx});
       k0 += nk;
