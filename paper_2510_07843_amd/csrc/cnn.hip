@@ -151,7 +151,9 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(Grid2 gd, const __bf16* _
     }
     if (!any) continue;  // uniform: e.g. the dy = +-1 taps of a one-row grid
     const bf16x8 b0 = reinterpret_cast<const bf16x8*>(w + (t * kCnnCh + r16) * kCnnCh)[kg];
-    const bf16x8 b1 = reinterpret_cast<const bf16x8*>(w + (t * kCnnCh + 16 + r16) * kCnnCh)[kg];
+    // the last layer has two output channels: its second tile of 16 is never read
+    const bf16x8* w1 = reinterpret_cast<const bf16x8*>(w + (t * kCnnCh + 16 + r16) * kCnnCh);
+    const bf16x8 b1 = MODE == 2 ? b0 : w1[kg];
 #pragma unroll
     for (int pp = 0; pp < 4; ++pp) {
       const int r = prow[pp] + dy, c = pcol[pp] + dx;
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(Grid2 gd, const __bf16* _
           for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.f;
         }
         acc[pp][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[pp][0], 0, 0, 0);
-        acc[pp][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[pp][1], 0, 0, 0);
+        if (MODE != 2) acc[pp][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[pp][1], 0, 0, 0);
       }
     }
   }
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(256) cnn_conv_kernel(Grid2 gd, const __bf16* _
     const int p = p0 + pp;
     if (p >= gd.npx) continue;
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
+    for (int tt = 0; tt < (MODE == 2 ? 1 : 2); ++tt) {
       const int o = 16 * tt + r16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
