@@ -86,7 +86,7 @@ def net_params(seed):
     return p
 
 
-GRIDS = [(1, 37, 20, 2), (2, 13, 16, 1), (3, 5, 33, 1), (1, 410, 64, 1)]
+GRIDS = [(1, 37, 20, 2), (2, 13, 16, 1), (3, 5, 33, 1), (1, 410, 64, 1), (5, 1, 16, 1), (3, 2, 17, 2)]
 
 
 @pytest.mark.parametrize("rows,cols,nimg,ngrp", GRIDS)
