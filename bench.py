@@ -220,6 +220,27 @@ def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, path, scs_hz,
             "data_re_per_slot": one.n_dsym * one.n_sc}
 
 
+def h2d_rate(torch, rx_host, ms_step, re):
+    """The received grids' upload over PCIe from pinned host memory, measured on a copy of
+    the batch's rx (not part of `value`: the library takes device buffers); with it the chain
+    rate if every step first uploaded its grids without overlap."""
+    src = torch.from_numpy(rx_host).reshape(-1).pin_memory()
+    dst = torch.empty(src.shape, dtype=src.dtype, device="cuda")
+    dst.copy_(src, non_blocking=True)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src, non_blocking=True)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = src.numel() * src.element_size()
+    return {"bytes": nbytes, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "chain_with_upload_re_per_s": re / ((ms_step + ms) * 1e-3)}
+
+
 def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96):
     """Train the pilot-estimate refinement on the GPU for the workload's DMRS grid (delay
     spread 30..300 ns, Doppler 0..500 Hz, SNR 0..30 dB) and choose its noise-variance gate by
@@ -649,7 +670,10 @@ def main():
             "GB/s": cc["bytes"] / (kern_ms[n] * 1e-3) / 1e9,
             "TFLOP/s": cc["flops"] / (kern_ms[n] * 1e-3) / 1e12,
             "bytes_per_launch": cc["bytes"], "flops_per_launch": cc["flops"]}
+    out["layer_re_per_s"] = value * shape.n_layers
+    out["llr_bits_per_s"] = value * shape.n_layers * shape.qm
     if not args.no_latency:
+        out["pcie_h2d"] = h2d_rate(torch, b["rx"], ms_step, re)
         out["slot_latency"] = slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec,
                                            path, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])
     if path == "receive":  # the three-call chain on the same batch, for comparison

@@ -55,7 +55,8 @@ struct TileCap<8, 3> {
   static constexpr int rows = kBatchLds, fac = kBatchFactSc * kBatchFactNP, fnp = kBatchFactNP,
                        aux = 2 * 8 + 1, fsc = kBatchFactSc;
   static constexpr bool one_occ = false;
-  static constexpr int stage_batch = 4;  // pilot estimates per thread whose loads are in flight together
+  // pilot estimates per thread whose loads are in flight together
+  static constexpr int stage_batch = 4;
 };
 template <>
 struct TileCap<4, 4> {  // two-occasion tiles of 16 x 4 fit 21 subcarriers

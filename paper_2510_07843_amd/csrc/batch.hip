@@ -187,7 +187,8 @@ __device__ __forceinline__ void solve_emit(const Geom& g, float* __restrict__ ll
 }
 
 template <int NL>
-__device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+__device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk,
+                                            int jlo, int nj,
                             const float2* __restrict__ lds, const SymTab& tab) {
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
@@ -249,7 +250,8 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
 // resource element then blends its Gram, forms z = (H0 + t D)^H y from the staged pairs and
 // finishes as the other paths do.
 template <int NL>
-__device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g, int k0, int nk, int jlo, int nj,
+__device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g, int k0, int nk,
+                                                 int jlo, int nj,
                                  const float2* __restrict__ rows, float4* __restrict__ pair,
                                  float2* __restrict__ gram, const SymTab& tab) {
   constexpr int NP = NL * (NL + 1) / 2;
@@ -344,7 +346,8 @@ __device__ __forceinline__ float2 row_interp(const float2* __restrict__ rows, in
 // tile's subcarriers into LDS.  fac[kk][tri(i, j)] holds L, aux[kk][0..NL) 1 / L_ii,
 // aux[kk][NL..2NL) d, aux[kk][2NL] 1 where the factorisation succeeded, else 0.
 template <int NL, class CAP>
-__device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
+__device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int k0, int nk,
+                                            int jlo,
                             const float2* __restrict__ rows, float2* __restrict__ fac,
                             float* __restrict__ aux) {
   constexpr int NP = NL * (NL + 1) / 2;
@@ -387,7 +390,8 @@ __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int
     for (int j = 0; j < NL; ++j) {
       float dj = G[tri(j, j)].x;
 #pragma unroll
-      for (int kq = 0; kq < j; ++kq) dj -= G[tri(j, kq)].x * G[tri(j, kq)].x + G[tri(j, kq)].y * G[tri(j, kq)].y;
+      for (int kq = 0; kq < j; ++kq)
+        dj -= G[tri(j, kq)].x * G[tri(j, kq)].x + G[tri(j, kq)].y * G[tri(j, kq)].y;
       ok = ok && (dj > kPivotRel * gd[j]);
       const float ljj = sqrtf(fmaxf(dj, FLT_MIN));
       const float inv = 1.f / ljj;
@@ -432,7 +436,8 @@ __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int
 // One occasion, per resource element with the staged factor: matched filter, substitutions,
 // unbiasing, LLRs.
 template <int NL, class CAP>
-__device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk, int jlo,
+__device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk,
+                                                 int jlo,
                                  const float2* __restrict__ rows,
                                  const float2* __restrict__ fac, const float* __restrict__ aux,
                                  const SymTab& tab) {
@@ -461,7 +466,8 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
     for (int r = 0; r < NR; ++r) {
       const float2 y = yrow[r];
 #pragma unroll
-      for (int i = 0; i < NL; ++i) cmac_c(z[i], row_interp(rows, RS, NL, r0[i], r1[i], a[i], r, i), y);
+      for (int i = 0; i < NL; ++i)
+        cmac_c(z[i], row_interp(rows, RS, NL, r0[i], r1[i], a[i], r, i), y);
     }
     const float2* L = fac + kk * CAP::fnp;
     const float* ax = aux + kk * CAP::aux;
@@ -870,7 +876,8 @@ int batch_tile_rows(const Geom& g, int k0, int nk) {
 }
 
 hipError_t launch_batch(void* plan, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<BatchHdr*>(plan));
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s,
+                     reinterpret_cast<BatchHdr*>(plan));
   hipLaunchKernelGGL(batch_kernel, dim3(blocks), dim3(256), 0, s, static_cast<char*>(plan));
   return hipGetLastError();
 }

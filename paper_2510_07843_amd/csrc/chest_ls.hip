@@ -82,9 +82,10 @@ __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* 
 }
 
 // Pilot resolution for small arrays: one block per (slot, occasion, run of up to jb
-// consecutive pilot indices), so that every block has work for its 256 threads.  Pilots j0 .. j0 + jb - 1 of every comb offset sit on the C jb contiguous
-// subcarriers C j0 .. C (j0 + jb) - 1, so the run's samples on each of the T DMRS symbols are
-// C jb Nr contiguous values: read with consecutive threads on consecutive values into LDS,
+// consecutive pilot indices), so that every block has work for its 256 threads.  Pilots
+// j0 .. j0 + jb - 1 of every comb offset sit on the C jb contiguous subcarriers
+// C j0 .. C (j0 + jb) - 1, so the run's samples on each of the T DMRS symbols are C jb Nr
+// contiguous values: read with consecutive threads on consecutive values into LDS,
 // rows padded by one value so that threads of different comb offsets read different banks.
 // The run's output rows h[j][rx][layer] (jb Nr Nl contiguous values) are written
 // contiguously.  jb = 1 takes chest_pilot_kernel, which needs fewer index divisions.
