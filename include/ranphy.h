@@ -251,6 +251,33 @@ RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params
 RANPHY_API int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilots,
                               const float* noise_var, float* llr, void* stream);
 
+/*
+ * Block floating point (BFP) compression of the received grid, for the fronthaul of
+ * distributed MIMO (Sec. VI-A proposes it and fixes no format; the format here is a reading):
+ *   - the grid rx [slot][symb][sc][rx] complex64 is cut into blocks of B consecutive antennas
+ *     of one resource element, B = 16 when n_rx is a multiple of 16, else B = n_rx (< 16);
+ *     any other antenna count returns RANPHY_ERR_UNSUPPORTED;
+ *   - a block's 2B real values v_i (I and Q interleaved, antenna order) share the exponent e,
+ *     the smallest integer with max |v_i| <= 255 * 2^e (0 for an all-zero block); each is
+ *     stored as the 9-bit two's complement mantissa m_i = round-half-even(v_i / 2^e), and
+ *     decompresses to m_i * 2^e, so the error is at most 2^(e-1) per value;
+ *   - a block is one 32-bit word holding e (two's complement), then ceil(18 B / 32) words of
+ *     mantissas, a little-endian bit stream with m_i in bits 9 i .. 9 i + 8 (unused high bits
+ *     zero); blocks follow the grid's resource elements, then antenna groups.
+ * For 16-antenna blocks that is 10 words for 128 bytes of FP32 samples (3.2x smaller).
+ *
+ * ranphy_bfp_words: the 32-bit words of the compressed grid of `d`, or a negative status.
+ * ranphy_bfp_compress: rx (device, 8-byte aligned) -> packed (device, 4-byte aligned,
+ *   ranphy_bfp_words(d) words).  Values must be finite.
+ * ranphy_bfp_decompress: packed -> rx; rx then holds exactly what the receive calls expect.
+ * Both are asynchronous on `stream`; host validation as for the other calls.
+ */
+RANPHY_API int64_t ranphy_bfp_words(const ranphy_slot_desc* d);
+RANPHY_API int ranphy_bfp_compress(const ranphy_slot_desc* d, const float* rx, uint32_t* packed,
+                                   void* stream);
+RANPHY_API int ranphy_bfp_decompress(const ranphy_slot_desc* d, const uint32_t* packed,
+                                     float* rx, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Many UEs of uneven allocations in one persistent launch (the scheduling and divergence
  * costs of SIMT processing the paper weighs in Sec. V): for every UE, LS estimation at the

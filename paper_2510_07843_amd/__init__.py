@@ -36,6 +36,7 @@ EXPORTED_SYMBOLS = (
     "ranphy_llr_demap", "ranphy_cnn_param_count", "ranphy_cnn_workspace_bytes",
     "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
     "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run", "ranphy_receive",
+    "ranphy_bfp_words", "ranphy_bfp_compress", "ranphy_bfp_decompress",
 )
 
 
@@ -113,10 +114,15 @@ def lib() -> ctypes.CDLL:
         L.ranphy_batch_plan.argtypes = [UE, I, I, P, I64]
         L.ranphy_batch_run.argtypes = [P, I, P]
         L.ranphy_receive.argtypes = [D, P, P, P, P, P]
+        L.ranphy_bfp_words.argtypes = [D]
+        L.ranphy_bfp_words.restype = I64
+        L.ranphy_bfp_compress.argtypes = [D, P, P, P]
+        L.ranphy_bfp_decompress.argtypes = [D, P, P, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
                   "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
                   "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_batch_plan",
-                  "ranphy_batch_run", "ranphy_receive"):
+                  "ranphy_batch_run", "ranphy_receive", "ranphy_bfp_compress",
+                  "ranphy_bfp_decompress"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -248,6 +254,41 @@ def receive(shape, rx: torch.Tensor, pilots: torch.Tensor, noise_var: torch.Tens
         _as_dev(noise_var, "noise_var", torch.float32, buffer_floats(d, BUF_NOISE_VAR)),
         _as_dev(llr, "llr", torch.float32, nl), _stream(stream)))
     return llr
+
+
+def bfp_words(shape) -> int:
+    """32-bit words of the block floating point form of the received grid of `shape`."""
+    n = int(lib().ranphy_bfp_words(ctypes.byref(desc_of(shape))))
+    if n < 0:
+        raise RanphyError("ranphy_bfp_words", n)
+    return n
+
+
+def bfp_compress(shape, rx: torch.Tensor, packed: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    """Block floating point form (int32 words holding the unsigned bit patterns) of the
+    received grid rx [slot][symb][sc][rx] complex64."""
+    d = desc_of(shape)
+    nw = bfp_words(shape)
+    if packed is None:
+        packed = torch.empty(nw, dtype=torch.int32, device=rx.device)
+    _check("ranphy_bfp_compress", lib().ranphy_bfp_compress(
+        ctypes.byref(d), _as_dev(rx, "rx", torch.complex64, buffer_floats(d, BUF_RX)),
+        _as_dev(packed, "packed", torch.int32, nw), _stream(stream)))
+    return packed
+
+
+def bfp_decompress(shape, packed: torch.Tensor, rx: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+    """The received grid [slot][symb][sc][rx] complex64 from its block floating point form."""
+    d = desc_of(shape)
+    nr = buffer_floats(d, BUF_RX)
+    if rx is None:
+        rx = torch.empty(nr // 2, dtype=torch.complex64, device=packed.device)
+    _check("ranphy_bfp_decompress", lib().ranphy_bfp_decompress(
+        ctypes.byref(d), _as_dev(packed, "packed", torch.int32, bfp_words(shape)),
+        _as_dev(rx, "rx", torch.complex64, nr), _stream(stream)))
+    return rx
 
 
 def llr_demap(shape, x: torch.Tensor, nv: torch.Tensor, llr: Optional[torch.Tensor] = None,

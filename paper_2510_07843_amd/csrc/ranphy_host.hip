@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "bfp.h"
 #include "geom.h"
 #include "ranphy.h"
 
@@ -327,6 +328,57 @@ int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilo
   return ranphy::status_of(ranphy::launch_receive(
       g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(pilots), noise_var,
       llr, nk, static_cast<hipStream_t>(stream)));
+}
+
+// ---- block floating point compression of the received grid --------------------------------
+
+namespace {
+// Blocks of the received grid of `g` (one per resource element and antenna group), or a
+// negative status when the antenna count has no block width.
+int64_t bfp_blocks(const Geom& g, int* b) {
+  *b = ranphy::bfp_block(g.n_rx);
+  if (*b == 0) return RANPHY_ERR_UNSUPPORTED;
+  return (int64_t)g.n_slots * g.n_symb * g.n_sc * (g.n_rx / *b);
+}
+}  // namespace
+
+int64_t ranphy_bfp_words(const ranphy_slot_desc* d) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  int b;
+  const int64_t n = bfp_blocks(g, &b);
+  return n < 0 ? n : n * ranphy::bfp_words_per_block(b);
+}
+
+int ranphy_bfp_compress(const ranphy_slot_desc* d, const float* rx, uint32_t* packed,
+                        void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  int b;
+  const int64_t n = bfp_blocks(g, &b);
+  if (n < 0) return (int)n;
+  if (n == 0) return RANPHY_OK;
+  if (!ranphy::aligned8(rx) || packed == nullptr || ((uintptr_t)packed & 3u))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(
+      ranphy::launch_bfp_compress(b, n, rx, packed, static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_bfp_decompress(const ranphy_slot_desc* d, const uint32_t* packed, float* rx,
+                          void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  int b;
+  const int64_t n = bfp_blocks(g, &b);
+  if (n < 0) return (int)n;
+  if (n == 0) return RANPHY_OK;
+  if (!ranphy::aligned8(rx) || packed == nullptr || ((uintptr_t)packed & 3u))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(
+      ranphy::launch_bfp_decompress(b, n, packed, rx, static_cast<hipStream_t>(stream)));
 }
 
 // ---- many UEs in one persistent launch ----------------------------------------------------

@@ -213,3 +213,31 @@ def test_batch_plan_validation(L):
     assert L.ranphy_batch_plan_bytes(bad, 1, 256) == -1
     assert L.ranphy_batch_run(None, 4, None) == -1
     assert L.ranphy_batch_run(P(0x10000), 0, None) == -1
+
+
+def test_bfp_sizes_and_validation(L):
+    P = ctypes.c_void_p
+    import oracle.bfp_ref as bref
+    for nr, nl in ((1, 1), (2, 2), (4, 4), (8, 4), (12, 4), (16, 8), (32, 8), (64, 16)):
+        kw = dict(n_rx=nr, n_layers=min(nl, nr), dmrs_comb=8 if nl > 8 else 4,
+                  dmrs_td=2 if nl > 4 else 1)
+        d = _desc(**kw)
+        b = bref.block_size(nr)
+        n_re = GOOD["n_slots"] * 14 * 12 * GOOD["n_prb"]
+        assert L.ranphy_bfp_words(ctypes.byref(d)) == n_re * (nr // b) * bref.words_per_block(b)
+    for nr in (17, 20, 40):  # neither below 16 nor a multiple of 16
+        d = _desc(n_rx=nr)
+        assert L.ranphy_bfp_words(ctypes.byref(d)) == -2
+        assert L.ranphy_bfp_compress(ctypes.byref(d), P(8), P(8), None) == -2
+        assert L.ranphy_bfp_decompress(ctypes.byref(d), P(8), P(8), None) == -2
+    d = _desc()
+    assert L.ranphy_bfp_words(None) == -1
+    assert L.ranphy_bfp_compress(None, P(8), P(8), None) == -1
+    assert L.ranphy_bfp_compress(ctypes.byref(d), P(0x1004), P(8), None) == -1  # rx
+    assert L.ranphy_bfp_compress(ctypes.byref(d), P(8), P(0x1002), None) == -1  # packed
+    assert L.ranphy_bfp_decompress(ctypes.byref(d), P(0), P(8), None) == -1
+    assert L.ranphy_bfp_decompress(ctypes.byref(d), P(8), P(0x1004), None) == -1
+    d0 = _desc(n_slots=0)
+    assert L.ranphy_bfp_words(ctypes.byref(d0)) == 0
+    assert L.ranphy_bfp_compress(ctypes.byref(d0), P(0), P(0), None) == 0
+    assert L.ranphy_bfp_decompress(ctypes.byref(d0), P(0), P(0), None) == 0

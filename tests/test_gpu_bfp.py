@@ -1,0 +1,178 @@
+"""GPU parity of the block floating point compression of the received grid (ranphy_bfp_*)
+against the oracle's definition (oracle/bfp_ref.py): packed words and decompressed samples
+bit-exact on seeded grids of every block width class, with ties, zeros, powers of two and
+extreme scales; the full-size 16- and 64-antenna grids sampled block by block, with the
+error bound and exponent minimality checked on every block; and the one-launch chain run on
+a decompressed grid against the oracle chain on the oracle's decompression of it."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.bfp_ref as bref
+import paper_2510_07843_amd as ranphy
+import synth
+from synth import SlotShape
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    ranphy.lib()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def shape_for(nr, n_prb=3, n_slots=2):
+    nl = min(nr, 2)
+    return SlotShape(n_prb=n_prb, n_symb=14, n_rx=nr, n_layers=nl, qm=2, dmrs_comb=2, dmrs_td=1,
+                     dmrs_sym0=(2,), n_slots=n_slots)
+
+
+def grid(shape, seed):
+    """Gaussian samples with a per-resource-element scale spread over twelve decades, some
+    all-zero resource elements and some exact zeros inside blocks."""
+    rng = np.random.default_rng(seed)
+    n_re = shape.n_slots * shape.n_symb * shape.n_sc
+    z = rng.standard_normal((n_re, shape.n_rx, 2))
+    z *= 10.0 ** rng.uniform(-6, 6, (n_re, 1, 1))
+    z[rng.random(n_re) < 0.05] = 0.0
+    z[rng.random(z.shape) < 0.02] = 0.0
+    return z.astype(np.float32).view(np.complex64).reshape(-1)
+
+
+def run(shape, rx):
+    t = torch.from_numpy(rx).cuda()
+    w = ranphy.bfp_compress(shape, t)
+    back = ranphy.bfp_decompress(shape, w)
+    torch.cuda.synchronize()
+    return w.cpu().numpy().view(np.uint32), back.cpu().numpy()
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+@pytest.mark.parametrize("nr", [1, 2, 3, 4, 7, 8, 12, 15, 16, 32, 64])
+def test_bit_exact_against_oracle(nr):
+    shape = shape_for(nr)
+    say(f"bfp nr={nr}")
+    rx = grid(shape, 100 + nr)
+    w, back = run(shape, rx)
+    wr = bref.compress(rx, nr)
+    assert w.shape == wr.shape == (ranphy.bfp_words(shape),)
+    assert np.array_equal(w, wr), np.flatnonzero(w != wr)[:8]
+    br = bref.decompress(wr, nr, rx.size)
+    assert np.array_equal(bits(back), bits(br))
+
+
+def test_ties_powers_of_two_and_extreme_scales():
+    """Blocks built on a chosen exponent: the peak exactly 255 * 2^e, the rest at half-odd
+    and half-even multiples of 2^e (round half to even both ways), powers of two, values just
+    past 255 * 2^e (the exponent steps up), and scales near the FP32 limits."""
+    nr = 16
+    shape = shape_for(nr, n_prb=1, n_slots=1)
+    n_re = shape.n_symb * shape.n_sc
+    rng = np.random.default_rng(7)
+    v = np.zeros((n_re, 2 * nr), np.float64)
+    for i in range(n_re):
+        e = int(rng.integers(-140, 118))
+        m = rng.integers(-255, 255, 2 * nr).astype(np.float64)
+        kind = i % 4
+        if kind == 0:
+            m = m + 0.5                      # ties: half-even rounding decides
+            m[0] = 255.0
+        elif kind == 1:
+            m = np.sign(m) * 2.0 ** rng.integers(0, 8, 2 * nr)
+        elif kind == 2:
+            m[0] = 255.0 + 2.0 ** -15        # just past the range of e (exact above 2^-126)
+            e = max(e, -100)
+        else:
+            m[0] = -255.0
+        v[i] = np.clip(m, -255.5, 255.0 + 2.0 ** -15) * 2.0 ** e
+    rx = v.astype(np.float32)
+    assert np.array_equal(rx.astype(np.float64), v)  # every test value exact in FP32
+    rx = rx.view(np.complex64).reshape(-1)
+    w, back = run(shape, rx)
+    wr = bref.compress(rx, nr)
+    assert np.array_equal(w, wr), np.flatnonzero(w != wr)[:8]
+    assert np.array_equal(bits(back), bits(bref.decompress(wr, nr, rx.size)))
+
+
+def block_checks(words, rx, nr):
+    """Properties of every block: decompressed values within 2^(e-1) of the input, and e the
+    smallest exponent whose range holds the block's peak."""
+    b = bref.block_size(nr)
+    wpb = bref.words_per_block(b)
+    e = words.reshape(-1, wpb)[:, 0].view(np.int32).astype(np.float64)
+    v = rx.view(np.float32).reshape(-1, 2 * b).astype(np.float64)
+    return e, v
+
+
+@pytest.mark.parametrize("name", ["c2", "m"])
+def test_full_size_grid_sampled(name):
+    c = synth.CONFIGS[name]
+    shape = c["shape"].with_slots(1)
+    say(f"bfp full size {name}: {shape}")
+    d = synth.make_slot(shape, synth.rng_for(c["config_id"], 0, 0), c["scs_hz"], c["pdp"],
+                        c["snr_db"][-1])
+    rx = np.ascontiguousarray(d["rx"]).reshape(-1)
+    w, back = run(shape, rx)
+    nr = shape.n_rx
+    b = bref.block_size(nr)
+    wpb = bref.words_per_block(b)
+    n_blocks = rx.size // b
+    assert w.size == n_blocks * wpb
+    # every block: the error bound and exponent minimality
+    e, v = block_checks(w, rx, nr)
+    vb = back.view(np.float32).reshape(-1, 2 * b).astype(np.float64)
+    step = np.ldexp(1.0, e.astype(np.int64))
+    assert np.all(np.abs(vb - v) <= 0.5 * step[:, None])
+    peak = np.abs(v).max(axis=1)
+    nz = peak > 0
+    assert np.all(peak[nz] <= 255.0 * step[nz]) and np.all(peak[nz] > 127.5 * step[nz])
+    sqnr = 10 * np.log10(np.sum(v ** 2) / np.sum((vb - v) ** 2))
+    say(f"  {n_blocks} blocks, SQNR {sqnr:.1f} dB")
+    # sampled blocks: words and samples bit-exact with the oracle
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(n_blocks, 3000, replace=False))
+    sub = rx.reshape(n_blocks, b)[pick].reshape(-1)
+    wr = bref.compress(sub, b)
+    assert np.array_equal(w.reshape(n_blocks, wpb)[pick].reshape(-1), wr)
+    assert np.array_equal(bits(back.reshape(n_blocks, b)[pick].reshape(-1)),
+                          bits(bref.decompress(wr, b, sub.size)))
+
+
+def test_receive_on_decompressed_grid():
+    """The one-launch chain on a decompressed 4 x 2 QPSK slot at 20 dB: every hard decision
+    is the transmitted bit, and the LLRs match the oracle chain run on the oracle's
+    decompression of the same words."""
+    c = synth.CONFIGS["c1"]
+    shape = c["shape"].with_slots(1)
+    d = synth.make_slot(shape, synth.rng_for(c["config_id"], 0, 0), c["scs_hz"], c["pdp"], 20.0)
+    rx = np.ascontiguousarray(d["rx"]).reshape(-1)
+    w = ranphy.bfp_compress(shape, torch.from_numpy(rx).cuda())
+    rxd = ranphy.bfp_decompress(shape, w)
+    pil = torch.from_numpy(np.ascontiguousarray(d["pilots"])).cuda().reshape(-1)
+    nvar = torch.tensor([d["noise_var"]], dtype=torch.float32, device="cuda")
+    llr = ranphy.receive(shape, rxd, pil, nvar)
+    torch.cuda.synchronize()
+    wr = bref.compress(rx, shape.n_rx)
+    assert np.array_equal(w.cpu().numpy().view(np.uint32), wr)
+    rxr = bref.decompress(wr, shape.n_rx, rx.size).reshape((1,) + d["rx"].shape)
+    hr = oracle.chest_ls(shape, rxr, d["pilots"][None], oracle.H_PILOT).astype(np.complex64)
+    xr, nvr = oracle.mmse_detect(shape, rxr, hr, oracle.H_PILOT,
+                                 np.array([d["noise_var"]], np.float32))
+    lr = oracle.llr_demap(shape, xr.astype(np.complex64), nvr.astype(np.float32))[0]
+    lg = llr.cpu().numpy().reshape(lr.shape)
+    assert np.array_equal((lg < 0).astype(np.uint8), d["bits"])
+    dl = np.abs(lg - lr) / (np.abs(lr) + 1e-3)
+    assert np.median(dl) < 1e-4 and np.quantile(dl, 0.999) < 1e-2, np.quantile(dl, 0.999)
