@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -220,7 +221,7 @@ def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, path, scs_hz,
             "data_re_per_slot": one.n_dsym * one.n_sc}
 
 
-def h2d_rate(torch, rx_host, ms_step, re):
+def h2d_rate(torch, rx_host, ms_step, re, ranphy=None, shape=None):
     """The received grids' upload over PCIe from pinned host memory, measured on a copy of
     the batch's rx (not part of `value`: the library takes device buffers); with it the chain
     rate if every step first uploaded its grids without overlap."""
@@ -237,8 +238,43 @@ def h2d_rate(torch, rx_host, ms_step, re):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
     nbytes = src.numel() * src.element_size()
-    return {"bytes": nbytes, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
-            "chain_with_upload_re_per_s": re / ((ms_step + ms) * 1e-3)}
+    out = {"bytes": nbytes, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+           "chain_with_upload_re_per_s": re / ((ms_step + ms) * 1e-3)}
+    if shape is not None:
+        out["bfp"] = bfp_upload(torch, ranphy, shape, dst, ms_step, re)
+    return out
+
+
+def bfp_upload(torch, ranphy, shape, rx_dev, ms_step, re):
+    """The same grids sent as block floating point words (16-antenna blocks, 9-bit mantissas,
+    shared exponent): upload of the words from pinned host memory, decompression on the GPU,
+    and the chain rate with both before every step (no overlap)."""
+    words = ranphy.bfp_compress(shape, rx_dev)
+    host = torch.empty(words.shape, dtype=words.dtype, pin_memory=True)
+    host.copy_(words)
+    back = torch.empty_like(rx_dev)
+    ranphy.bfp_decompress(shape, words, back)
+    torch.cuda.synchronize()
+    err = (back - rx_dev).abs().pow(2).sum().item()
+    sqnr = 10.0 * math.log10(rx_dev.abs().pow(2).sum().item() / err) if err > 0 else None
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    reps = 3
+    ev[0].record()
+    for _ in range(reps):
+        words.copy_(host, non_blocking=True)
+    ev[1].record()
+    for _ in range(reps):
+        ranphy.bfp_decompress(shape, words, back)
+    ev[2].record()
+    torch.cuda.synchronize()
+    up = ev[0].elapsed_time(ev[1]) / reps
+    dec = ev[1].elapsed_time(ev[2]) / reps
+    nb = words.numel() * 4
+    return {"bytes": nb, "ratio": round(rx_dev.numel() * 8 / nb, 3), "upload_ms": round(up, 4),
+            "decompress_ms": round(dec, 4),
+            "decompress_GB/s": round((nb + rx_dev.numel() * 8) / (dec * 1e-3) / 1e9, 1),
+            "sqnr_db": None if sqnr is None else round(sqnr, 1),
+            "chain_with_upload_re_per_s": re / ((ms_step + up + dec) * 1e-3)}
 
 
 def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96):
@@ -681,7 +717,7 @@ def main():
     out["layer_re_per_s"] = value * shape.n_layers
     out["llr_bits_per_s"] = value * shape.n_layers * shape.qm
     if not args.no_latency:
-        out["pcie_h2d"] = h2d_rate(torch, b["rx"], ms_step, re)
+        out["pcie_h2d"] = h2d_rate(torch, b["rx"], ms_step, re, ranphy, shape)
         out["slot_latency"] = slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec,
                                            path, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])
     if path == "receive":  # the three-call chain on the same batch, for comparison
