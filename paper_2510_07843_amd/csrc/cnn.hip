@@ -338,11 +338,187 @@ __global__ void cnn_adam_kernel(float* __restrict__ p, const float* __restrict__
   p[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
+// ---- inference on one-row grids: the four layers in one kernel ----------------------------
+// A one-row grid (one DMRS occasion) makes every layer a 1 x 3 correlation along the pilots
+// (the dy = +-1 taps read the zero padding).  One wave holds kFuseSeg consecutive pixels of
+// 16 images in registers, one B operand (bf16x8) per pixel, and runs the four layers there:
+// layer l computes pixels l + 1 .. kFuseSeg - 2 - l of the segment, so the last writes the
+// kFuseOut pixels 4 .. kFuseSeg - 5.  Products are transposed relative to cnn_conv_kernel:
+// A = the tap's weights (rows = 16 output channels), B = activations (columns = 16 images,
+// K = 32 input channels), so a lane's accumulators (image l & 15, output channels 4 (l >> 4)
+// + v of each 16-channel tile) are, after bias and ReLU, exactly its B operand for the next
+// layer when the K slots 8 q + e of lane group q hold input channels 4 q + e (e < 4) and
+// 16 + 4 q + e - 4 (e >= 4).  Pixels outside the image are zero at every layer's input.
+constexpr int kFuseSeg = 24;
+constexpr int kFuseOut = kFuseSeg - 2 * kCnnLayers;
+constexpr int kFuseW = kCnnTaps * kCnnCh * kCnnCh;  // packed weights of one layer
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// x [g][p][img][2] FP32 -> xn [g][p][img][2] BF16, divided by sigma of the group; groups the
+// gate keeps plain are skipped (the fused kernel copies them).
+__global__ void cnn_norm_kernel(const float2* __restrict__ x, bf16x2* __restrict__ xn, int64_t n,
+                                int64_t per_group, const float* __restrict__ nv, float gate_min) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int64_t g = e / per_group;
+  const float r = inv_sigma(nv, g);
+  if (!(nv == nullptr || (nv[g] >= gate_min && r > 0.f))) return;
+  const float2 v = x[e];
+  bf16x2 o;
+  o[0] = (__bf16)(v.x * r);
+  o[1] = (__bf16)(v.y * r);
+  xn[e] = o;
+}
+
+// The A operand of one output channel's packed row wf[t][o][0 .. 31] for lane group q.
+__device__ __forceinline__ bf16x8 fused_w(const __bf16* row, int q) {
+  const bf16x4 lo = *reinterpret_cast<const bf16x4*>(row + 4 * q);
+  const bf16x4 hi = *reinterpret_cast<const bf16x4*>(row + 16 + 4 * q);
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    r[e] = lo[e];
+    r[4 + e] = hi[e];
+  }
+  return r;
+}
+
+// relu(lo), relu(hi) as two BF16 in one word: round to nearest even, then the ReLU as a
+// 16-bit integer max with 0 (a BF16 is negative exactly when its sign bit is set, and the
+// order of non-negative BF16 bit patterns is that of their values).
+__device__ __forceinline__ unsigned relu_bf16x2(float lo, float hi) {
+  typedef float floatx2 __attribute__((ext_vector_type(2)));
+  typedef short shortx2 __attribute__((ext_vector_type(2)));
+  const bf16x2 v = __builtin_convertvector((floatx2){lo, hi}, bf16x2);
+  const shortx2 m = __builtin_elementwise_max(__builtin_bit_cast(shortx2, v), (shortx2){0, 0});
+  return __builtin_bit_cast(unsigned, m);
+}
+
+// Hidden layer L (0..2) in place: act[p] <- relu(b + sum_dx W[3 + dx] act[p - 1 + dx]) for
+// p = L + 1 .. kFuseSeg - 2 - L (the bias seeds the accumulators); pixel p sits at column
+// pos0 + p, and pixels outside the image are zeroed afterwards.
+template <int L>
+__device__ __forceinline__ void fused_hidden(bf16x8 (&act)[kFuseSeg], const __bf16* __restrict__ wf,
+                                             const float* __restrict__ params, int pos0, int cols,
+                                             int j, int q) {
+  typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
+  const __bf16* wl = wf + L * kFuseW;
+  bf16x8 wa[3][2];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+      wa[dx][tt] = fused_w(wl + ((3 + dx) * kCnnCh + 16 * tt + j) * kCnnCh, q);
+  const float* bias = params + L * kCnnLayerParams + kFuseW;
+  floatx4 b0, b1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    b0[v] = bias[4 * q + v];
+    b1[v] = bias[16 + 4 * q + v];
+  }
+  constexpr int lo = L + 1, hi = kFuseSeg - 1 - L;
+  bf16x8 held;
+#pragma unroll
+  for (int p = lo; p < hi; ++p) {
+    floatx4 a0 = b0, a1 = b1;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[dx][0], act[p - 1 + dx], a0, 0, 0, 0);
+      a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[dx][1], act[p - 1 + dx], a1, 0, 0, 0);
+    }
+    const uintx4 o = {relu_bf16x2(a0[0], a0[1]), relu_bf16x2(a0[2], a0[3]),
+                      relu_bf16x2(a1[0], a1[1]), relu_bf16x2(a1[2], a1[3])};
+    if (p > lo) act[p - 1] = held;  // pixel p - 1's input was last read just above
+    held = __builtin_bit_cast(bf16x8, o);
+  }
+  act[hi - 1] = held;
+  if (pos0 + lo < 0 || pos0 + hi > cols) {  // wave-uniform: a segment at an image edge
+#pragma unroll
+    for (int p = lo; p < hi; ++p)
+      if ((unsigned)(pos0 + p) >= (unsigned)cols) act[p] = bf16x8{};
+  }
+}
+
+// out = x + sigma y for the groups the gate refines, out = x for the others; out may alias x
+// (each lane reads x only at the pixels it writes; the halo comes from xn).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) cnn_fused1_kernel(Grid2 gd, const __bf16* __restrict__ wf,
+                                                         const float* __restrict__ params,
+                                                         const bf16x2* __restrict__ xn,
+                                                         const float2* x, float2* out,
+                                                         const float* __restrict__ nv,
+                                                         float gate_min) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int nseg = (gd.cols + kFuseOut - 1) / kFuseOut;
+  const int nib = (gd.nimg + 15) >> 4;
+  if (wave >= (int64_t)gd.ngrp * nseg * nib) return;  // wave-uniform
+  const int ib = (int)(wave % nib);
+  const int64_t rest = wave / nib;
+  const int seg = (int)(rest % nseg);
+  const int64_t grp = rest / nseg;
+  const int j = lane & 15, q = lane >> 4;
+  const int img = ib * 16 + j;
+  const bool mine = q == 0 && img < gd.nimg;  // the lanes that own image img's two channels
+  const int c0 = seg * kFuseOut;
+  const int pos0 = c0 - kCnnLayers;           // column of segment pixel 0
+  const int64_t gbase = grp * gd.npx;
+  const float r = inv_sigma(nv, grp);
+  const bool keep = nv == nullptr || (nv[grp] >= gate_min && r > 0.f);
+  if (!keep) {  // wave-uniform: the plain estimate
+    if (mine)
+      for (int p = 0; p < kFuseOut && c0 + p < gd.cols; ++p) {
+        const int64_t e = (gbase + c0 + p) * gd.nimg + img;
+        out[e] = x[e];
+      }
+    return;
+  }
+  bf16x8 act[kFuseSeg];
+#pragma unroll
+  for (int p = 0; p < kFuseSeg; ++p) {
+    bf16x8 a;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a[e] = (__bf16)0.f;
+    const int pos = pos0 + p;
+    if (mine && (unsigned)pos < (unsigned)gd.cols) {
+      const bf16x2 v = xn[(gbase + pos) * gd.nimg + img];
+      a[0] = v[0];
+      a[1] = v[1];
+    }
+    act[p] = a;
+  }
+  fused_hidden<0>(act, wf, params, pos0, gd.cols, j, q);
+  fused_hidden<1>(act, wf, params, pos0, gd.cols, j, q);
+  fused_hidden<2>(act, wf, params, pos0, gd.cols, j, q);
+  // last layer: output channels 0 and 1 (tile 0, lanes q = 0, registers 0 and 1)
+  const __bf16* wl = wf + 3 * kFuseW;
+  bf16x8 wa[3];
+#pragma unroll
+  for (int dx = 0; dx < 3; ++dx) wa[dx] = fused_w(wl + ((3 + dx) * kCnnCh + j) * kCnnCh, q);
+  const float* bias = params + 3 * kCnnLayerParams + kFuseW;
+  const floatx4 b3 = {bias[0], bias[1], 0.f, 0.f};
+  const float sigma = 1.f / r;
+#pragma unroll
+  for (int p = kCnnLayers; p < kFuseSeg - kCnnLayers; ++p) {
+    floatx4 a0 = b3;
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx)
+      a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[dx], act[p - 1 + dx], a0, 0, 0, 0);
+    const int pos = pos0 + p;
+    if (mine && pos < gd.cols) {
+      const int64_t e = (gbase + pos) * gd.nimg + img;
+      const float2 xr = x[e];
+      out[e] = make_float2(fmaf(a0[0], sigma, xr.x), fmaf(a0[1], sigma, xr.y));
+    }
+  }
+}
+
 // Workspace carving (every piece 256-byte aligned).
 struct CnnWs {
   __bf16* wf;     // [4][9][32][32]
   __bf16* wb;     // [4][9][32][32]
   __bf16* act[4]; // a0 .. a3
+  __bf16* xn;     // one-row inference: [g][p][img][2] normalised BF16 input
   __bf16* dz[2];
   float* out;     // [g][p][img][2]
   float* part;    // weight-gradient partials
@@ -365,9 +541,11 @@ CnnWs carve(void* base, const Grid2& gd, bool train) {
   const int64_t wsz = (int64_t)kCnnLayers * kCnnTaps * kCnnCh * kCnnCh * 2;
   w.wf = reinterpret_cast<__bf16*>(take(wsz));
   w.wb = reinterpret_cast<__bf16*>(take(train ? wsz : 0));
-  const int nact = train ? 4 : 2;
+  const bool fused = !train && gd.rows == 1;  // inference on one-row grids: one kernel
+  const int nact = train ? 4 : (fused ? 0 : 2);
   for (int i = 0; i < 4; ++i)
     w.act[i] = i < nact ? reinterpret_cast<__bf16*>(take(nq * kCnnCh * 2)) : nullptr;
+  w.xn = reinterpret_cast<__bf16*>(take(fused ? nq * 2 * 2 : 0));
   for (int i = 0; i < 2; ++i)
     w.dz[i] = train ? reinterpret_cast<__bf16*>(take(nq * kCnnCh * 2)) : nullptr;
   w.out = reinterpret_cast<float*>(take(train ? nq * 2 * 4 : 0));
@@ -398,6 +576,18 @@ hipError_t forward(const Grid2& gd, const float* params, const float* x, float* 
   const int64_t nq = (int64_t)gd.ngrp * gd.npx * gd.nimg;
   hipLaunchKernelGGL(cnn_pack_kernel, dim3((kCnnLayers * kWsz + 255) / 256), dim3(256), 0, s,
                      params, w.wf, w.wb);
+  if (w.xn != nullptr) {  // inference on a one-row grid
+    hipLaunchKernelGGL(cnn_norm_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float2*>(x), reinterpret_cast<bf16x2*>(w.xn), nq,
+                       (int64_t)gd.npx * gd.nimg, nv, gate_min);
+    const int64_t waves = (int64_t)gd.ngrp * ((gd.cols + kFuseOut - 1) / kFuseOut) *
+                          ((gd.nimg + 15) / 16);
+    hipLaunchKernelGGL(cnn_fused1_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, gd,
+                       w.wf, params, reinterpret_cast<const bf16x2*>(w.xn),
+                       reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(out), nv,
+                       gate_min);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(cnn_input_kernel, dim3((unsigned)((nq * 4 + 255) / 256)), dim3(256), 0, s,
                      x, w.act[0], nq, (int64_t)gd.npx * gd.nimg, nv);
   // training keeps a0 .. a3; inference ping-pongs between two buffers

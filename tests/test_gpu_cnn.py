@@ -86,7 +86,8 @@ def net_params(seed):
     return p
 
 
-GRIDS = [(1, 37, 20, 2), (2, 13, 16, 1), (3, 5, 33, 1), (1, 410, 64, 1), (5, 1, 16, 1), (3, 2, 17, 2)]
+GRIDS = [(1, 37, 20, 2), (2, 13, 16, 1), (3, 5, 33, 1), (1, 410, 64, 1), (5, 1, 16, 1), (3, 2, 17, 2),
+         (1, 1, 16, 1), (1, 16, 5, 2), (1, 17, 33, 1), (1, 2, 48, 3)]
 
 
 @pytest.mark.parametrize("rows,cols,nimg,ngrp", GRIDS)
@@ -137,6 +138,24 @@ def test_gradients_match_oracle(rows, cols, nimg, ngrp):
     W3 = gv[3 * 9248:3 * 9248 + 9216].reshape(9, 32, 32)
     assert not W3[:, :, 2:].any() and not gv[3 * 9248 + 9216 + 2:].any()
     assert np.array_equal(full, gv)
+
+
+def test_one_row_forward_in_place():
+    """out may alias x: the one-row inference kernel reads its neighbours' pixels from a
+    normalised copy, so the in-place result equals the out-of-place one bit for bit, gated
+    groups included."""
+    rows, cols, nimg, ngrp = 1, 53, 40, 3
+    p = torch.from_numpy(pack(net_params(5))).cuda()
+    rng = np.random.default_rng(4)
+    x = torch.from_numpy(rng.standard_normal(ngrp * cols * nimg * 2).astype(np.float32)).cuda()
+    nv = torch.tensor([0.3, 1e-6, 0.02], dtype=torch.float32, device="cuda")
+    ref = ranphy.cnn_forward(p, x, rows, cols, nimg, ngrp, noise_var=nv, min_noise_var=1e-4)
+    y = x.clone()
+    ranphy.cnn_forward(p, y, rows, cols, nimg, ngrp, out=y, noise_var=nv, min_noise_var=1e-4)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    g1 = slice(cols * nimg * 2, 2 * cols * nimg * 2)
+    assert torch.equal(y[g1], x[g1])  # below the gate
 
 
 def test_noise_normalised_forward_and_gradients():
