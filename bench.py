@@ -741,8 +741,10 @@ def main():
         if not args.no_learned:
             params, min_nv, report = train_refinement(torch, ranphy, synth, shape)
             nimg = shape.n_rx * shape.n_layers
+            # one pass over the batch where the grid has one row (small workspace), else 35 slots
             wsb = ranphy.cnn_workspace_bytes(shape.n_occ, shape.n_pilot, nimg,
-                                             min(shape.n_slots, 35), False)
+                                             shape.n_slots if shape.n_occ == 1
+                                             else min(shape.n_slots, 35), False)
             ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
             v_ms, v_k = run_timed(ranphy.PREC_FP32, fused, refine=(params, min_nv, ws))
             variants["learned_fp32"] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,

@@ -201,8 +201,12 @@ RANPHY_API int ranphy_llr_demap(const ranphy_slot_desc* d, const float* x, const
  * Tensors: x, target, out [group][pixel = row * cols + col][image][2] FP32 (real, imaginary).
  * A pilot-resolution estimate h[slot][occ][j][rx][layer] is such a tensor with
  * group = slot, rows = occasions, cols = pilots, image = rx * n_layers + layer.
+ * Limits: rows * cols <= 2^20 pixels, n_img <= 2^20 and rows * cols * n_img <= 2^30 per group
+ * (else RANPHY_ERR_UNSUPPORTED).
  * Workspace: device memory of ranphy_cnn_workspace_bytes(..) bytes, 256-byte aligned,
- * owned by the caller; its contents need not be initialised.  Errors as above.
+ * owned by the caller; its contents need not be initialised.  Inference on a one-row grid
+ * runs the four layers in one kernel and needs only the packed weights and a BF16 copy of
+ * the input; other grids and training keep every layer's activations.  Errors as above.
  * ------------------------------------------------------------------------------------- */
 RANPHY_API int64_t ranphy_cnn_param_count(void);
 /* Workspace bytes for a forward pass (train = 0) or a gradient pass (train = 1). */

@@ -357,13 +357,15 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // x [g][p][img][2] FP32 -> xn [g][p][img][2] BF16, divided by sigma of the group; groups the
 // gate keeps plain are skipped (the fused kernel copies them).
-__global__ void cnn_norm_kernel(const float2* __restrict__ x, bf16x2* __restrict__ xn, int64_t n,
-                                int64_t per_group, const float* __restrict__ nv, float gate_min) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int64_t g = e / per_group;
+// Group g0 + blockIdx.y, elements blockIdx.x * 256 + threadIdx.x of its per_group.
+__global__ void cnn_norm_kernel(const float2* __restrict__ x, bf16x2* __restrict__ xn, int64_t g0,
+                                int per_group, const float* __restrict__ nv, float gate_min) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per_group) return;
+  const int64_t g = g0 + blockIdx.y;
   const float r = inv_sigma(nv, g);
   if (!(nv == nullptr || (nv[g] >= gate_min && r > 0.f))) return;
+  const int64_t e = g * per_group + i;
   const float2 v = x[e];
   bf16x2 o;
   o[0] = (__bf16)(v.x * r);
@@ -465,12 +467,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   const int64_t gbase = grp * gd.npx;
   const float r = inv_sigma(nv, grp);
   const bool keep = nv == nullptr || (nv[grp] >= gate_min && r > 0.f);
-  if (!keep) {  // wave-uniform: the plain estimate
-    if (mine)
-      for (int p = 0; p < kFuseOut && c0 + p < gd.cols; ++p) {
-        const int64_t e = (gbase + c0 + p) * gd.nimg + img;
-        out[e] = x[e];
-      }
+  // The residual x at the wave's output pixels is loaded in full before any store: out may
+  // alias x, so a load placed after a store could not be issued before that store completes.
+  float2 res[kFuseOut];
+  auto load_res = [&]() {
+#pragma unroll
+    for (int p = 0; p < kFuseOut; ++p) {
+      res[p] = make_float2(0.f, 0.f);
+      if (mine && c0 + p < gd.cols) res[p] = x[(gbase + c0 + p) * gd.nimg + img];
+    }
+  };
+  if (!keep) {  // wave-uniform: the plain estimate (nothing to do in place)
+    if (out != x) {
+      load_res();
+#pragma unroll
+      for (int p = 0; p < kFuseOut; ++p)
+        if (mine && c0 + p < gd.cols) out[(gbase + c0 + p) * gd.nimg + img] = res[p];
+    }
     return;
   }
   bf16x8 act[kFuseSeg];
@@ -495,6 +508,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
   bf16x8 wa[3];
 #pragma unroll
   for (int dx = 0; dx < 3; ++dx) wa[dx] = fused_w(wl + ((3 + dx) * kCnnCh + j) * kCnnCh, q);
+  load_res();
   const float* bias = params + 3 * kCnnLayerParams + kFuseW;
   const floatx4 b3 = {bias[0], bias[1], 0.f, 0.f};
   const float sigma = 1.f / r;
@@ -506,9 +520,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[dx], act[p - 1 + dx], a0, 0, 0, 0);
     const int pos = pos0 + p;
     if (mine && pos < gd.cols) {
-      const int64_t e = (gbase + pos) * gd.nimg + img;
-      const float2 xr = x[e];
-      out[e] = make_float2(fmaf(a0[0], sigma, xr.x), fmaf(a0[1], sigma, xr.y));
+      const float2 xr = res[p - kCnnLayers];
+      out[(gbase + pos) * gd.nimg + img] =
+          make_float2(fmaf(a0[0], sigma, xr.x), fmaf(a0[1], sigma, xr.y));
     }
   }
 }
@@ -577,9 +591,13 @@ hipError_t forward(const Grid2& gd, const float* params, const float* x, float* 
   hipLaunchKernelGGL(cnn_pack_kernel, dim3((kCnnLayers * kWsz + 255) / 256), dim3(256), 0, s,
                      params, w.wf, w.wb);
   if (w.xn != nullptr) {  // inference on a one-row grid
-    hipLaunchKernelGGL(cnn_norm_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s,
-                       reinterpret_cast<const float2*>(x), reinterpret_cast<bf16x2*>(w.xn), nq,
-                       (int64_t)gd.npx * gd.nimg, nv, gate_min);
+    const int per_group = gd.npx * gd.nimg;
+    for (int g0 = 0; g0 < gd.ngrp; g0 += 65535) {
+      const int ng = gd.ngrp - g0 < 65535 ? gd.ngrp - g0 : 65535;
+      hipLaunchKernelGGL(cnn_norm_kernel, dim3((unsigned)((per_group + 255) / 256), ng), dim3(256),
+                         0, s, reinterpret_cast<const float2*>(x), reinterpret_cast<bf16x2*>(w.xn),
+                         (int64_t)g0, per_group, nv, gate_min);
+    }
     const int64_t waves = (int64_t)gd.ngrp * ((gd.cols + kFuseOut - 1) / kFuseOut) *
                           ((gd.nimg + 15) / 16);
     hipLaunchKernelGGL(cnn_fused1_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, gd,

@@ -231,7 +231,9 @@ int64_t ranphy_cnn_workspace_bytes(int rows, int cols, int n_img, int n_groups, 
 static int cnn_check(int rows, int cols, int n_img, int n_groups, const void* ws,
                      int64_t ws_bytes, int train) {
   if (rows < 1 || cols < 1 || n_img < 1 || n_groups < 0) return RANPHY_ERR_INVALID;
-  if ((int64_t)rows * cols > (1 << 20) || n_img > (1 << 20)) return RANPHY_ERR_UNSUPPORTED;
+  if ((int64_t)rows * cols > (1 << 20) || n_img > (1 << 20) ||
+      (int64_t)rows * cols * n_img > (1 << 30))
+    return RANPHY_ERR_UNSUPPORTED;
   if (ws == nullptr || ((uintptr_t)ws & 255u) ||
       ws_bytes < ranphy::cnn_workspace_bytes(rows, cols, n_img, n_groups, train != 0))
     return RANPHY_ERR_INVALID;

@@ -241,3 +241,36 @@ def test_bfp_sizes_and_validation(L):
     assert L.ranphy_bfp_words(ctypes.byref(d0)) == 0
     assert L.ranphy_bfp_compress(ctypes.byref(d0), P(0), P(0), None) == 0
     assert L.ranphy_bfp_decompress(ctypes.byref(d0), P(0), P(0), None) == 0
+
+
+def test_cnn_validation(L):
+    P = ctypes.c_void_p
+    L.ranphy_cnn_workspace_bytes.restype = ctypes.c_int64
+    fwd = L.ranphy_cnn_forward
+    fwd.argtypes = [P, P, P, ctypes.c_float, P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                    ctypes.c_int, P, ctypes.c_int64, P]
+    ok = dict(rows=1, cols=410, n_img=1024, n_groups=2)
+
+    def call(ws=0x10000, wsb=1 << 40, nv=None, gate=0.0, **kw):
+        a = dict(ok, **kw)
+        return fwd(P(0x1000), P(0x1000), P(nv), gate, P(0x1000), a["rows"], a["cols"],
+                   a["n_img"], a["n_groups"], P(ws), wsb, None)
+
+    # sizes: one-row inference needs far less than the layered form (two activation tensors)
+    one = L.ranphy_cnn_workspace_bytes(1, 410, 1024, 2, 0)
+    two = L.ranphy_cnn_workspace_bytes(2, 205, 1024, 2, 0)
+    train = L.ranphy_cnn_workspace_bytes(1, 410, 1024, 2, 1)
+    assert 0 < one < two < train
+    assert one >= 2 * 410 * 1024 * 4  # the BF16 input copy
+    assert L.ranphy_cnn_workspace_bytes(0, 410, 1024, 2, 0) == -1
+    # limits and validation happen before any launch
+    assert call(cols=1 << 15, n_img=1 << 16) == -2   # 2^31 pixel-images per group
+    assert call(cols=(1 << 20) + 1, n_img=1) == -2
+    assert call(n_img=0) == -1
+    assert call(ws=0) == -1
+    assert call(ws=0x10010) == -1                      # workspace not 256-byte aligned
+    assert call(wsb=one - 1) == -1                     # workspace too small
+    wz = L.ranphy_cnn_workspace_bytes(1, 410, 1024, 0, 0)  # the packed weights alone
+    assert call(n_groups=0, wsb=wz - 1) == -1
+    assert call(n_groups=0, wsb=wz) == 0                # no groups: a no-op
+    assert call(gate=-1.0) == -1
