@@ -221,7 +221,7 @@ def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, path, scs_hz,
             "data_re_per_slot": one.n_dsym * one.n_sc}
 
 
-def h2d_rate(torch, rx_host, ms_step, re, ranphy=None, shape=None):
+def h2d_rate(torch, rx_host, ms_step, re, ranphy=None, shape=None, fused_step=None):
     """The received grids' upload over PCIe from pinned host memory, measured on a copy of
     the batch's rx (not part of `value`: the library takes device buffers); with it the chain
     rate if every step first uploaded its grids without overlap."""
@@ -241,14 +241,16 @@ def h2d_rate(torch, rx_host, ms_step, re, ranphy=None, shape=None):
     out = {"bytes": nbytes, "ms": round(ms, 4), "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1),
            "chain_with_upload_re_per_s": re / ((ms_step + ms) * 1e-3)}
     if shape is not None:
-        out["bfp"] = bfp_upload(torch, ranphy, shape, dst, ms_step, re)
+        out["bfp"] = bfp_upload(torch, ranphy, shape, dst, ms_step, re, fused_step)
     return out
 
 
-def bfp_upload(torch, ranphy, shape, rx_dev, ms_step, re):
+def bfp_upload(torch, ranphy, shape, rx_dev, ms_step, re, fused_step=None):
     """The same grids sent as block floating point words (16-antenna blocks, 9-bit mantissas,
     shared exponent): upload of the words from pinned host memory, decompression on the GPU,
-    and the chain rate with both before every step (no overlap)."""
+    and the chain rate with both before every step (no overlap).  With `fused_step(words)`
+    (the estimator and detector reading the words themselves) also that chain's own time and
+    its rate with the upload."""
     words = ranphy.bfp_compress(shape, rx_dev)
     host = torch.empty(words.shape, dtype=words.dtype, pin_memory=True)
     host.copy_(words)
@@ -270,11 +272,26 @@ def bfp_upload(torch, ranphy, shape, rx_dev, ms_step, re):
     up = ev[0].elapsed_time(ev[1]) / reps
     dec = ev[1].elapsed_time(ev[2]) / reps
     nb = words.numel() * 4
-    return {"bytes": nb, "ratio": round(rx_dev.numel() * 8 / nb, 3), "upload_ms": round(up, 4),
-            "decompress_ms": round(dec, 4),
-            "decompress_GB/s": round((nb + rx_dev.numel() * 8) / (dec * 1e-3) / 1e9, 1),
-            "sqnr_db": None if sqnr is None else round(sqnr, 1),
-            "chain_with_upload_re_per_s": re / ((ms_step + up + dec) * 1e-3)}
+    out = {"bytes": nb, "ratio": round(rx_dev.numel() * 8 / nb, 3), "upload_ms": round(up, 4),
+           "decompress_ms": round(dec, 4),
+           "decompress_GB/s": round((nb + rx_dev.numel() * 8) / (dec * 1e-3) / 1e9, 1),
+           "sqnr_db": None if sqnr is None else round(sqnr, 1),
+           "chain_with_upload_re_per_s": re / ((ms_step + up + dec) * 1e-3)}
+    if fused_step is not None:
+        fused_step(words)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            fused_step(words)
+        e1.record()
+        torch.cuda.synchronize()
+        fm = e0.elapsed_time(e1) / reps
+        out["fused_chain_ms"] = round(fm, 4)
+        out["fused_chain_re_per_s"] = re / (fm * 1e-3)
+        out["fused_chain_with_upload_re_per_s"] = re / ((up + fm) * 1e-3)
+    return out
 
 
 def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96):
@@ -717,7 +734,12 @@ def main():
     out["layer_re_per_s"] = value * shape.n_layers
     out["llr_bits_per_s"] = value * shape.n_layers * shape.qm
     if not args.no_latency:
-        out["pcie_h2d"] = h2d_rate(torch, b["rx"], ms_step, re, ranphy, shape)
+        fused_step = None
+        if path == "fused" and h_res == ranphy.H_PILOT:
+            def fused_step(words):  # the decompression inside the estimator's and detector's loads
+                ranphy.chest_ls_bfp(shape, words, pil, h=h)
+                ranphy.mmse_llr_bfp(shape, words, h, nvar, llr=llr, precision=prec)
+        out["pcie_h2d"] = h2d_rate(torch, b["rx"], ms_step, re, ranphy, shape, fused_step)
         out["slot_latency"] = slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec,
                                            path, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])
     if path == "receive":  # the three-call chain on the same batch, for comparison

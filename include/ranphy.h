@@ -281,6 +281,22 @@ RANPHY_API int ranphy_bfp_compress(const ranphy_slot_desc* d, const float* rx, u
                                    void* stream);
 RANPHY_API int ranphy_bfp_decompress(const ranphy_slot_desc* d, const uint32_t* packed,
                                      float* rx, void* stream);
+/*
+ * The decompression fused into the loads of the receive path (the fronthaul delivers the
+ * words, the grid is never expanded in device memory):
+ * ranphy_chest_ls_bfp: ranphy_chest_ls with the received grid given as BFP words (packed:
+ *   device, 4-byte aligned, ranphy_bfp_words(d) words); every sample is decoded where the
+ *   estimator reads it.  Antenna counts without a block width: RANPHY_ERR_UNSUPPORTED.
+ * ranphy_mmse_llr_bfp: ranphy_mmse_llr with the received grid given as BFP words (packed:
+ *   8-byte aligned); its shapes (n_rx a multiple of 16, so one lane's 16 antennas of one
+ *   symbol are one block), each block decoded in registers inside the detector.
+ * Both give bit for bit what the FP32 calls give on ranphy_bfp_decompress's output.
+ */
+RANPHY_API int ranphy_chest_ls_bfp(const ranphy_slot_desc* d, const uint32_t* packed,
+                                   const float* pilots, float* h, int h_res, void* stream);
+RANPHY_API int ranphy_mmse_llr_bfp(const ranphy_slot_desc* d, const uint32_t* packed,
+                                   const float* h, int h_res, const float* noise_var, float* x,
+                                   float* nv, float* llr, int precision, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Many UEs of uneven allocations in one persistent launch (the scheduling and divergence

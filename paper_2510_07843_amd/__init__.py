@@ -36,7 +36,8 @@ EXPORTED_SYMBOLS = (
     "ranphy_llr_demap", "ranphy_cnn_param_count", "ranphy_cnn_workspace_bytes",
     "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
     "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run", "ranphy_receive",
-    "ranphy_bfp_words", "ranphy_bfp_compress", "ranphy_bfp_decompress",
+    "ranphy_bfp_words", "ranphy_bfp_compress", "ranphy_bfp_decompress", "ranphy_chest_ls_bfp",
+    "ranphy_mmse_llr_bfp",
 )
 
 
@@ -118,11 +119,13 @@ def lib() -> ctypes.CDLL:
         L.ranphy_bfp_words.restype = I64
         L.ranphy_bfp_compress.argtypes = [D, P, P, P]
         L.ranphy_bfp_decompress.argtypes = [D, P, P, P]
+        L.ranphy_chest_ls_bfp.argtypes = [D, P, P, P, ctypes.c_int, P]
+        L.ranphy_mmse_llr_bfp.argtypes = [D, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
                   "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
                   "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_batch_plan",
                   "ranphy_batch_run", "ranphy_receive", "ranphy_bfp_compress",
-                  "ranphy_bfp_decompress"):
+                  "ranphy_bfp_decompress", "ranphy_chest_ls_bfp", "ranphy_mmse_llr_bfp"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -289,6 +292,45 @@ def bfp_decompress(shape, packed: torch.Tensor, rx: Optional[torch.Tensor] = Non
         ctypes.byref(d), _as_dev(packed, "packed", torch.int32, bfp_words(shape)),
         _as_dev(rx, "rx", torch.complex64, nr), _stream(stream)))
     return rx
+
+
+def chest_ls_bfp(shape, packed: torch.Tensor, pilots: torch.Tensor,
+                 h: Optional[torch.Tensor] = None, h_res: int = H_PILOT,
+                 stream=None) -> torch.Tensor:
+    """chest_ls reading the received grid in block floating point form (bfp_compress)."""
+    d = desc_of(shape)
+    nh = buffer_floats(d, BUF_H, h_res)
+    if h is None:
+        h = torch.empty(nh // 2, dtype=torch.complex64, device=packed.device)
+    args = (_as_dev(packed, "packed", torch.int32, bfp_words(shape)),
+            _as_dev(pilots, "pilots", torch.complex64, buffer_floats(d, BUF_PILOTS)),
+            _as_dev(h, "h", torch.complex64, nh))
+    _check("ranphy_chest_ls_bfp",
+           lib().ranphy_chest_ls_bfp(ctypes.byref(d), *args, h_res, _stream(stream)))
+    return h
+
+
+def mmse_llr_bfp(shape, packed: torch.Tensor, h: torch.Tensor, noise_var: torch.Tensor,
+                 h_res: int = H_PILOT, llr: Optional[torch.Tensor] = None,
+                 x: Optional[torch.Tensor] = None, nv: Optional[torch.Tensor] = None,
+                 precision: int = PREC_FP32, stream=None) -> torch.Tensor:
+    """mmse_llr reading the received grid in block floating point form, decoded in the
+    detector's load; returns the LLRs."""
+    d = desc_of(shape)
+    nl = buffer_floats(d, BUF_LLR)
+    if llr is None:
+        llr = torch.empty(nl, dtype=torch.float32, device=packed.device)
+    if (x is None) != (nv is None):
+        raise ValueError("x and nv are given together or not at all")
+    args = (_as_dev(packed, "packed", torch.int32, bfp_words(shape)),
+            _as_dev(h, "h", torch.complex64, buffer_floats(d, BUF_H, h_res)))
+    pn = _as_dev(noise_var, "noise_var", torch.float32, buffer_floats(d, BUF_NOISE_VAR))
+    px = None if x is None else _as_dev(x, "x", torch.complex64, buffer_floats(d, BUF_X))
+    pv = None if nv is None else _as_dev(nv, "nv", torch.float32, buffer_floats(d, BUF_NV))
+    pl = _as_dev(llr, "llr", torch.float32, nl)
+    _check("ranphy_mmse_llr_bfp", lib().ranphy_mmse_llr_bfp(
+        ctypes.byref(d), *args, h_res, pn, px, pv, pl, precision, _stream(stream)))
+    return llr
 
 
 def llr_demap(shape, x: torch.Tensor, nv: torch.Tensor, llr: Optional[torch.Tensor] = None,

@@ -11,7 +11,34 @@
 namespace ranphy {
 namespace {
 
-template <int T>
+// Sample of antenna r (of NR) at resource element re of the received grid: complex64
+// (RXF = 0) or block floating point (RXF = 1: blocks of B = 16 antennas, or NR below 16, each
+// one exponent word then the 9-bit two's complement mantissas of the block's I, Q values as
+// a little-endian bit stream, value m 2^e).  Antenna i of a block has its two fields in bits
+// 18 i .. 18 i + 17, inside the block's last word, so the second word is read only when the
+// fields reach it.
+template <int RXF>
+__device__ __forceinline__ float2 rx_at(const float2* __restrict__ rx, int64_t re, int NR,
+                                        int r) {
+  if constexpr (RXF == 0) {
+    return rx[re * NR + r];
+  } else {
+    const bool wide = NR >= 16;
+    const int B = wide ? 16 : NR;
+    const int W = 1 + (18 * B + 31) / 32;
+    const int i = wide ? (r & 15) : r;
+    const unsigned* b = reinterpret_cast<const unsigned*>(rx) +
+                        (re * (wide ? (NR >> 4) : 1) + (wide ? (r >> 4) : 0)) * W;
+    const int bit = 18 * i, word = 1 + (bit >> 5), sh = bit & 31;
+    const unsigned long long f =
+        (((unsigned long long)b[word + (sh > 14 ? 1 : 0)] << 32) | b[word]) >> sh;
+    const int e = (int)b[0];
+    return make_float2(ldexpf((float)((int)((unsigned)f << 23) >> 23), e),
+                       ldexpf((float)((int)((unsigned)(f >> 9) << 23) >> 23), e));
+  }
+}
+
+template <int T, int RXF>
 __device__ __forceinline__ float2 ls_at(const Geom& g, const float2* __restrict__ rx,
                                         const float2* __restrict__ pil, int64_t slot, int o,
                                         int j, int r, int p) {
@@ -20,7 +47,7 @@ __device__ __forceinline__ float2 ls_at(const Geom& g, const float2* __restrict_
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int s = g.sym0[o] + t;
-    const float2 y = rx[((slot * g.n_symb + s) * g.n_sc + k) * g.n_rx + r];
+    const float2 y = rx_at<RXF>(rx, (slot * g.n_symb + s) * g.n_sc + k, g.n_rx, r);
     const float2 q = pil[(((slot * g.n_occ + o) * T + t) * g.n_pilot + j) * g.n_layers + p];
     const float2 m = cmulc(q, y);  // y * conj(q)
     acc.x += m.x;
@@ -35,7 +62,7 @@ __device__ __forceinline__ float2 ls_at(const Geom& g, const float2* __restrict_
 // (C x Nr contiguous values per symbol) are read with consecutive threads on consecutive
 // values into LDS, rows padded by one value so that threads of different comb offsets read
 // different banks, and the Nr x Nl output row h[j][rx][layer] is written contiguously.
-template <int T>
+template <int T, int RXF>
 __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* __restrict__ rx,
                                                           const float2* __restrict__ pil,
                                                           float2* __restrict__ h) {
@@ -54,7 +81,7 @@ __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* 
     const int r = rem - c * NR;
     const int k = C * j + c;
     float2 v = make_float2(0.f, 0.f);
-    if (k < g.n_sc) v = rx[((slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k) * NR + r];
+    if (k < g.n_sc) v = rx_at<RXF>(rx, (slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k, NR, r);
     ys[(t * C + c) * (NR + 1) + r] = v;
   }
   if (threadIdx.x < T * NL) {
@@ -92,7 +119,7 @@ __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* 
 constexpr int kRunPadded = 520;  // C jb (Nr + 1) <= 520 values per DMRS symbol
 constexpr int kRunPilots = 512;  // T jb Nl <= 512 pilot values
 
-template <int T>
+template <int T, int RXF>
 __global__ void __launch_bounds__(256) chest_run_kernel(Geom g, const float2* __restrict__ rx,
                                                           const float2* __restrict__ pil,
                                                           float2* __restrict__ h, int jb) {
@@ -115,7 +142,7 @@ __global__ void __launch_bounds__(256) chest_run_kernel(Geom g, const float2* __
     const int r = rem - kk * NR;
     const int k = C * j0 + kk;
     float2 v = make_float2(0.f, 0.f);
-    if (k < g.n_sc) v = rx[((slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k) * NR + r];
+    if (k < g.n_sc) v = rx_at<RXF>(rx, (slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k, NR, r);
     ys[(t * C * jb + kk) * pitch + r] = v;
   }
   for (int f = threadIdx.x; f < T * nj * NL; f += 256) {
@@ -148,7 +175,7 @@ __global__ void __launch_bounds__(256) chest_run_kernel(Geom g, const float2* __
   }
 }
 
-template <int T>
+template <int T, int RXF>
 __global__ void __launch_bounds__(256) chest_full_kernel(Geom g, const float2* __restrict__ rx,
                                                          const float2* __restrict__ pil,
                                                          float2* __restrict__ h) {
@@ -166,15 +193,14 @@ __global__ void __launch_bounds__(256) chest_full_kernel(Geom g, const float2* _
   int j0, j1;
   float a;
   freq_rule(g, p, k, j0, j1, a);
-  const float2 v0 = ls_at<T>(g, rx, pil, slot, o, j0, r, p);
-  const float2 v1 = ls_at<T>(g, rx, pil, slot, o, j1, r, p);
+  const float2 v0 = ls_at<T, RXF>(g, rx, pil, slot, o, j0, r, p);
+  const float2 v1 = ls_at<T, RXF>(g, rx, pil, slot, o, j1, r, p);
   h[e] = make_float2(v0.x + a * (v1.x - v0.x), v0.y + a * (v1.y - v0.y));
 }
 
-}  // namespace
-
-hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots, float2* h,
-                           int h_res, hipStream_t s) {
+template <int RXF>
+hipError_t launch_chest_rxf(const Geom& g, const float2* rx, const float2* pilots, float2* h,
+                            int h_res, hipStream_t s) {
   const int64_t per = (int64_t)g.n_occ * g.n_rx * g.n_layers * (h_res == 0 ? g.n_pilot : g.n_sc);
   const int64_t total = per * g.n_slots;
   if (total == 0) return hipSuccess;
@@ -185,18 +211,31 @@ hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots
     const int nrun = (g.n_pilot + jb - 1) / jb;
     const dim3 pgrid((unsigned)((int64_t)g.n_slots * g.n_occ * nrun));
     if (jb == 1) {
-      if (g.td == 1) hipLaunchKernelGGL(chest_pilot_kernel<1>, pgrid, block, 0, s, g, rx, pilots, h);
-      else hipLaunchKernelGGL(chest_pilot_kernel<2>, pgrid, block, 0, s, g, rx, pilots, h);
+      if (g.td == 1)
+        hipLaunchKernelGGL((chest_pilot_kernel<1, RXF>), pgrid, block, 0, s, g, rx, pilots, h);
+      else
+        hipLaunchKernelGGL((chest_pilot_kernel<2, RXF>), pgrid, block, 0, s, g, rx, pilots, h);
     } else if (g.td == 1) {
-      hipLaunchKernelGGL(chest_run_kernel<1>, pgrid, block, 0, s, g, rx, pilots, h, jb);
+      hipLaunchKernelGGL((chest_run_kernel<1, RXF>), pgrid, block, 0, s, g, rx, pilots, h, jb);
     } else {
-      hipLaunchKernelGGL(chest_run_kernel<2>, pgrid, block, 0, s, g, rx, pilots, h, jb);
+      hipLaunchKernelGGL((chest_run_kernel<2, RXF>), pgrid, block, 0, s, g, rx, pilots, h, jb);
     }
   } else {
-    if (g.td == 1) hipLaunchKernelGGL(chest_full_kernel<1>, grid, block, 0, s, g, rx, pilots, h);
-    else hipLaunchKernelGGL(chest_full_kernel<2>, grid, block, 0, s, g, rx, pilots, h);
+    if (g.td == 1)
+      hipLaunchKernelGGL((chest_full_kernel<1, RXF>), grid, block, 0, s, g, rx, pilots, h);
+    else
+      hipLaunchKernelGGL((chest_full_kernel<2, RXF>), grid, block, 0, s, g, rx, pilots, h);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+// rx: the complex64 grid, or (bfp) its block floating point words.
+hipError_t launch_chest_ls(const Geom& g, const float2* rx, bool bfp, const float2* pilots,
+                           float2* h, int h_res, hipStream_t s) {
+  return bfp ? launch_chest_rxf<1>(g, rx, pilots, h, h_res, s)
+             : launch_chest_rxf<0>(g, rx, pilots, h, h_res, s);
 }
 
 }  // namespace ranphy

@@ -67,8 +67,9 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
 }
 
 // Kernel launchers (one translation unit each).  They return a hipError_t.
-hipError_t launch_chest_ls(const Geom& g, const float2* rx, const float2* pilots, float2* h,
-                           int h_res, hipStream_t s);
+// rx: the complex64 grid, or with bfp its block floating point words (ranphy_bfp_compress).
+hipError_t launch_chest_ls(const Geom& g, const float2* rx, bool bfp, const float2* pilots,
+                           float2* h, int h_res, hipStream_t s);
 hipError_t launch_mmse_re(const Geom& g, const float2* rx, const float2* h, int h_res,
                           const float* noise_var, float2* x, float* nv, hipStream_t s);
 // One thread per subcarrier (one DMRS occasion, Nr in {1,2,4,8}, Nl <= 8, Nr Nl <= 64).

@@ -24,6 +24,13 @@
 // and both substitutions in one sweep over the matrix, which suits a 64-lane wave holding a
 // 16 x 16 matrix as 4 values per lane.
 //
+// The received grid may also arrive in block floating point form (RXF = 1): 16-antenna
+// blocks of 10 words, a shared exponent e then the 9-bit two's complement mantissas m of the
+// block's 32 reals (I and Q interleaved) as a little-endian bit stream, each value m 2^e.
+// A lane's 16 antennas of one symbol are exactly one block, read as five 8-byte loads and
+// decoded in registers just before the matched filter; the decoded values equal those of
+// the separate decompression kernel bit for bit, so the results do too.
+//
 // MFMA operand layouts (16x16x4, single block), lane l = 16 q + c:
 //   A[i][kk] <- lane (i + 16 kk);  B[kk][j] <- lane (j + 16 kk);  D[i][j] -> lane (j + 16 (i/4)),
 //   register i % 4.  The K index of step s is mapped to receive antenna 16 q + s, so that
@@ -172,6 +179,37 @@ __device__ __forceinline__ double uniform_read(double v, int lane) {
 __device__ __forceinline__ float recip(float p) { return __builtin_amdgcn_rcpf(p); }
 __device__ __forceinline__ double recip(double p) { return 1.0 / p; }
 
+// ---- block floating point received grid (16-antenna blocks) --------------------------------
+constexpr int kBfpWords = 10;  // exponent + 288 bits of mantissas
+// Value f (0..31: I, Q of antenna f / 2) of a block held in w[0..9], w[0] the exponent.
+template <int F>
+__device__ __forceinline__ float bfp_value(const unsigned (&w)[kBfpWords]) {
+  constexpr int bit = 9 * F, word = 1 + (bit >> 5), sh = bit & 31;
+  unsigned m = w[word] >> sh;
+  if constexpr (sh > 23) m |= w[word + 1] << (32 - sh);
+  return ldexpf((float)((int)(m << 23) >> 23), (int)w[0]);
+}
+template <int F>
+__device__ __forceinline__ void bfp_decode(const unsigned (&w)[kBfpWords], float (&yr)[16],
+                                           float (&yi)[16]) {
+  if constexpr (F < 16) {
+    yr[F] = bfp_value<2 * F>(w);
+    yi[F] = bfp_value<2 * F + 1>(w);
+    bfp_decode<F + 1>(w, yr, yi);
+  }
+}
+// Sample of antenna r (of NR, a multiple of 16) at resource element re of a BFP grid.
+__device__ __forceinline__ float2 bfp_sample(const unsigned* __restrict__ words, int64_t re,
+                                             int NR, int r) {
+  const unsigned* b = words + (re * (NR >> 4) + (r >> 4)) * kBfpWords;
+  const int i = r & 15, bit = 18 * i, word = 1 + (bit >> 5), sh = bit & 31;
+  const unsigned long long f =
+      (((unsigned long long)b[word + (sh > 14 ? 1 : 0)] << 32) | b[word]) >> sh;
+  const int e = (int)b[0];
+  return make_float2(ldexpf((float)((int)((unsigned)f << 23) >> 23), e),
+                     ldexpf((float)((int)((unsigned)(f >> 9) << 23) >> 23), e));
+}
+
 // One Gauss-Jordan step on pivot K, with the pivot-column scaling deferred.  Lane (q, c)
 // holds R[4q+v][c] in (ar[v], ai[v]); the matrix of the textbook in-place elimination is
 // A[i][j] = R[i][j] s_j, where s_j = 1 until column j has been the pivot column and
@@ -294,7 +332,7 @@ __device__ __forceinline__ void gj_f64(double (&ar)[4], double (&ai)[4], int q, 
 // (a, a multiple of 1/C, is exact in FP32).  Rolled loops and cross-lane reads keep it
 // within the FP32 path's registers: it runs only for the rare subcarriers whose FP32
 // condition estimate exceeds kCondMax (or whose FP32 elimination failed).
-template <int HRES, int NL>
+template <int HRES, int NL, int RXF>
 __device__ __forceinline__ void solve_f64(const Geom& g, const float2* rows, int jlo, int k0,
                                           int k, int slot, const float2* __restrict__ rx,
                                           float s2f, int q, int c, float (&xo)[8],
@@ -359,11 +397,13 @@ __device__ __forceinline__ void solve_f64(const Geom& g, const float2* rows, int
   asm volatile("" : "+v"(cl));
   const int d = cl < ND ? cl : ND - 1;
   const int sym = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
-  const float2* __restrict__ y = rx + ((int64_t)(slot * g.n_symb + sym) * g.n_sc + k) * NR;
+  const int64_t re = (int64_t)(slot * g.n_symb + sym) * g.n_sc + k;
+  const float2* __restrict__ y = rx + re * NR;
   double zr[4] = {0, 0, 0, 0}, zi[4] = {0, 0, 0, 0};
 #pragma unroll 1
   for (int r = 0; r < NR; ++r) {
-    const float2 yy = y[r];
+    const float2 yy =
+        RXF == 0 ? y[r] : bfp_sample(reinterpret_cast<const unsigned*>(rx), re, NR, r);
     const double yr = yy.x, yi = yy.y;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -478,7 +518,7 @@ __device__ __forceinline__ void emit_llr(float* __restrict__ llr, float* stage, 
   }
 }
 
-template <int HRES, int NL, int PREC>
+template <int HRES, int NL, int PREC, int RXF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
                                                         const float* __restrict__ nvar,
@@ -544,13 +584,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   // only the channel, so this load's latency is hidden behind them.  (Issued after the
   // block's channel copy, which every wave of the block waits for.)
   float4 yv[8];
+  unsigned yw[kBfpWords];  // RXF = 1: the lane's block, decoded before the matched filter
   {
     const int d = c < ND ? c : ND - 1;
     const int s = (d < g.sym0[0]) ? d : d + g.td;  // one occasion: skip its T DMRS symbols
-    const float4* __restrict__ src = reinterpret_cast<const float4*>(
-        rx + ((int64_t)(slot * g.n_symb + s) * g.n_sc + k) * NR + 16 * qc);
+    const int64_t re = (int64_t)(slot * g.n_symb + s) * g.n_sc + k;
+    if constexpr (RXF == 0) {
+      const float4* __restrict__ src = reinterpret_cast<const float4*>(rx + re * NR + 16 * qc);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) yv[i] = src[i];
+      for (int i = 0; i < 8; ++i) yv[i] = src[i];
+    } else {
+      const uint2* __restrict__ src = reinterpret_cast<const uint2*>(
+          reinterpret_cast<const unsigned*>(rx) + (re * (NR >> 4) + qc) * kBfpWords);
+#pragma unroll
+      for (int i = 0; i < kBfpWords / 2; ++i) {
+        const uint2 v = src[i];
+        yw[2 * i] = v.x;
+        yw[2 * i + 1] = v.y;
+      }
+    }
   }
   const float s2 = nvar[slot];
 
@@ -650,12 +702,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     // ---- 5. matched filter Z = H^H Y on the matrix cores ----------------------------------
     {
       float yr[16], yi[16];
+      if constexpr (RXF == 0) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        yr[2 * i] = yv[i].x;
-        yi[2 * i] = yv[i].y;
-        yr[2 * i + 1] = yv[i].z;
-        yi[2 * i + 1] = yv[i].w;
+        for (int i = 0; i < 8; ++i) {
+          yr[2 * i] = yv[i].x;
+          yi[2 * i] = yv[i].y;
+          yr[2 * i + 1] = yv[i].z;
+          yi[2 * i + 1] = yv[i].w;
+        }
+      } else {
+        bfp_decode<0>(yw, yr, yi);
       }
       if constexpr (PREC == kPrecF32) {
         // Three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
@@ -714,7 +770,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
       vo[v] = sd * im;
     }
   }
-  if (f64) solve_f64<HRES, NL>(g, lds_h, jlo, k0, k, slot, rx, s2, q, c, xo, vo);
+  if (f64) solve_f64<HRES, NL, RXF>(g, lds_h, jlo, k0, k, slot, rx, s2, q, c, xo, vo);
   const int d = c;
   const bool mine = live && d < ND && 4 * q < NL;
   const int64_t o = ((int64_t)(slot * ND + (d < ND ? d : 0)) * g.n_sc + k) * NL;
@@ -751,36 +807,40 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 }
 
 template <int HRES, int NL, int PREC>
-void launch_one(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
-                float2* x, float* nv, float* llr, hipStream_t s) {
-  hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC>), grid, dim3(256), 0, s, g, rx, h, nvar,
-                     x, nv, llr);
+void launch_one(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
+                const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
+  if (bfp)
+    hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC, 1>), grid, dim3(256), 0, s, g, rx, h,
+                       nvar, x, nv, llr);
+  else
+    hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC, 0>), grid, dim3(256), 0, s, g, rx, h,
+                       nvar, x, nv, llr);
 }
 
 template <int HRES, int PREC>
-void launch_nl(const Geom& g, dim3 grid, const float2* rx, const float2* h, const float* nvar,
-               float2* x, float* nv, float* llr, hipStream_t s) {
+void launch_nl(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
+               const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
   switch (g.n_layers) {
-    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
-    default: launch_one<HRES, 16, PREC>(g, grid, rx, h, nvar, x, nv, llr, s); break;
+    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    default: launch_one<HRES, 16, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
   }
 }
 
 template <int PREC>
-void launch_prec(const Geom& g, dim3 grid, const float2* rx, const float2* h, int h_res,
-                 const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
-  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, h, nvar, x, nv, llr, s);
-  else launch_nl<1, PREC>(g, grid, rx, h, nvar, x, nv, llr, s);
+void launch_prec(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
+                 int h_res, const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
+  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s);
+  else launch_nl<1, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s);
 }
 
 }  // namespace
@@ -795,16 +855,16 @@ bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void
          g.n_rx % 16 == 0 && g.n_rx <= 64 && g.n_dsym <= 16;
 }
 
-hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
-                            const float* nvar, float2* x, float* nv, float* llr, int prec,
-                            hipStream_t s) {
+hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, bool bfp, const float2* h,
+                            int h_res, const float* nvar, float2* x, float* nv, float* llr,
+                            int prec, hipStream_t s) {
   const int64_t waves = (int64_t)g.n_slots * g.n_sc;
   const int64_t blocks = (waves + 3) / 4;
   const dim3 grid((unsigned)((blocks + kXcds - 1) / kXcds * kXcds));
   switch (prec) {
-    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, h, h_res, nvar, x, nv, llr, s); break;
-    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, h, h_res, nvar, x, nv, llr, s); break;
-    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, h, h_res, nvar, x, nv, llr, s); break;
+    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, bfp, h, h_res, nvar, x, nv, llr, s); break;
+    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, bfp, h, h_res, nvar, x, nv, llr, s); break;
+    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, bfp, h, h_res, nvar, x, nv, llr, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -16,9 +16,10 @@
 
 namespace ranphy {
 
-hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, const float2* h, int h_res,
-                            const float* noise_var, float2* x, float* nv, float* llr, int prec,
-                            hipStream_t s);
+// rx: the complex64 grid, or with bfp its block floating point words (16-antenna blocks).
+hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, bool bfp, const float2* h,
+                            int h_res, const float* noise_var, float2* x, float* nv, float* llr,
+                            int prec, hipStream_t s);
 bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
                         const void* nv, const void* llr);
 
@@ -144,7 +145,23 @@ int ranphy_chest_ls(const ranphy_slot_desc* d, const float* rx, const float* pil
   if (!ranphy::aligned8(rx) || !ranphy::aligned8(pilots) || !ranphy::aligned8(h))
     return RANPHY_ERR_INVALID;
   return ranphy::status_of(ranphy::launch_chest_ls(
-      g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(pilots),
+      g, reinterpret_cast<const float2*>(rx), false, reinterpret_cast<const float2*>(pilots),
+      reinterpret_cast<float2*>(h), h_res, static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_chest_ls_bfp(const ranphy_slot_desc* d, const uint32_t* packed, const float* pilots,
+                        float* h, int h_res, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+  if (ranphy::bfp_block(g.n_rx) == 0) return RANPHY_ERR_UNSUPPORTED;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (packed == nullptr || ((uintptr_t)packed & 3u) || !ranphy::aligned8(pilots) ||
+      !ranphy::aligned8(h))
+    return RANPHY_ERR_INVALID;
+  return ranphy::status_of(ranphy::launch_chest_ls(
+      g, reinterpret_cast<const float2*>(packed), true, reinterpret_cast<const float2*>(pilots),
       reinterpret_cast<float2*>(h), h_res, static_cast<hipStream_t>(stream)));
 }
 
@@ -170,7 +187,8 @@ int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx, const fl
   if (precision != RANPHY_PREC_FP32 && !mfma) return RANPHY_ERR_UNSUPPORTED;
   if (mfma)
     return ranphy::status_of(
-        ranphy::launch_mmse_mfma(g, rx2, h2, h_res, noise_var, x2, nv, nullptr, precision, s));
+        ranphy::launch_mmse_mfma(g, rx2, false, h2, h_res, noise_var, x2, nv, nullptr, precision,
+                                 s));
   // Small arrays with one DMRS occasion: one thread per subcarrier shares the Gram and its
   // factorisation over the data symbols, once the batch has a subcarrier for every lane of
   // the chip (256 CUs x 4 SIMDs x 64 lanes); smaller batches (a single slot) finish sooner
@@ -204,8 +222,33 @@ int ranphy_mmse_llr(const ranphy_slot_desc* d, const float* rx, const float* h, 
     return RANPHY_ERR_INVALID;
   if (!ranphy::mmse_mfma_eligible(g, rx, h, x, nv, llr)) return RANPHY_ERR_UNSUPPORTED;
   return ranphy::status_of(ranphy::launch_mmse_mfma(
-      g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(h), h_res,
+      g, reinterpret_cast<const float2*>(rx), false, reinterpret_cast<const float2*>(h), h_res,
       noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
+      static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_mmse_llr_bfp(const ranphy_slot_desc* d, const uint32_t* packed, const float* h,
+                        int h_res, const float* noise_var, float* x, float* nv, float* llr,
+                        int precision, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
+  if (precision != RANPHY_PREC_FP32 && precision != RANPHY_PREC_FP16 &&
+      precision != RANPHY_PREC_BF16)
+    return RANPHY_ERR_INVALID;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if ((x == nullptr) != (nv == nullptr)) return RANPHY_ERR_INVALID;
+  if (!ranphy::aligned8(packed) || !ranphy::aligned8(h) || !ranphy::aligned8(llr) ||
+      (x != nullptr && (!ranphy::aligned8(x) || !ranphy::aligned8(nv))) ||
+      noise_var == nullptr || ((uintptr_t)noise_var & 3u))
+    return RANPHY_ERR_INVALID;
+  // the matrix-core shapes (n_rx a multiple of 16: 16-antenna blocks); the words need only
+  // 8-byte alignment
+  if (!ranphy::mmse_mfma_eligible(g, nullptr, h, x, nv, llr)) return RANPHY_ERR_UNSUPPORTED;
+  return ranphy::status_of(ranphy::launch_mmse_mfma(
+      g, reinterpret_cast<const float2*>(packed), true, reinterpret_cast<const float2*>(h),
+      h_res, noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
       static_cast<hipStream_t>(stream)));
 }
 

@@ -274,3 +274,28 @@ def test_cnn_validation(L):
     assert call(n_groups=0, wsb=wz - 1) == -1
     assert call(n_groups=0, wsb=wz) == 0                # no groups: a no-op
     assert call(gate=-1.0) == -1
+
+
+def test_fused_bfp_validation(L):
+    P = ctypes.c_void_p
+    d = _desc(n_rx=20, n_layers=4)  # no block width for 20 antennas
+    assert L.ranphy_chest_ls_bfp(ctypes.byref(d), P(8), P(8), P(8), 0, None) == -2
+    d = _desc()  # 8 x 4: estimator yes, matrix-core detector no
+    assert L.ranphy_chest_ls_bfp(ctypes.byref(d), P(0), P(8), P(8), 0, None) == -1
+    assert L.ranphy_chest_ls_bfp(ctypes.byref(d), P(0x1002), P(8), P(8), 0, None) == -1
+    assert L.ranphy_chest_ls_bfp(ctypes.byref(d), P(8), P(8), P(8), 2, None) == -1
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(d), P(16), P(16), 0, P(16), None, None, P(16), 0,
+                                 None) == -2
+    m = _desc(n_rx=64, n_layers=16, dmrs_comb=8, dmrs_td=2, qm=6)
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(0x1004), P(16), 0, P(16), None, None, P(16),
+                                 0, None) == -1  # words not 8-byte aligned
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(16), 0, P(16), P(16), None, P(16), 0,
+                                 None) == -1  # x without nv
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(16), 0, P(16), None, None, P(16), 3,
+                                 None) == -1  # precision
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(0x1008), 0, P(16), None, None, P(16),
+                                 0, None) == -2  # channel not 16-byte aligned: not the MFMA form
+    m0 = _desc(n_rx=64, n_layers=16, dmrs_comb=8, dmrs_td=2, qm=6, n_slots=0)
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m0), P(0), P(0), 0, P(0), None, None, P(0), 0,
+                                 None) == 0
+    assert L.ranphy_chest_ls_bfp(ctypes.byref(m0), P(0), P(0), P(0), 0, None) == 0

@@ -176,3 +176,111 @@ def test_receive_on_decompressed_grid():
     assert np.array_equal((lg < 0).astype(np.uint8), d["bits"])
     dl = np.abs(lg - lr) / (np.abs(lr) + 1e-3)
     assert np.median(dl) < 1e-4 and np.quantile(dl, 0.999) < 1e-2, np.quantile(dl, 0.999)
+
+
+# ---- decompression fused into the loads of the estimator and the detector ----------------
+
+def _slot(shape, seed, snr=20.0):
+    d = synth.make_slot(shape.with_slots(1), np.random.default_rng(seed), 30e3, ("exp", 1e-7), snr)
+    return d
+
+
+def _batch(shape, seed):
+    """Slots of `shape` (n_slots of them) stacked, with words from the oracle's compressor."""
+    ds = [_slot(shape, seed + i) for i in range(shape.n_slots)]
+    rx = np.ascontiguousarray(np.stack([d["rx"] for d in ds])).reshape(-1)
+    pil = np.ascontiguousarray(np.stack([d["pilots"] for d in ds])).reshape(-1)
+    nv = np.array([d["noise_var"] for d in ds], np.float32)
+    words = bref.compress(rx, shape.n_rx).view(np.int32)
+    return (torch.from_numpy(words).cuda(), torch.from_numpy(pil).cuda(),
+            torch.from_numpy(nv).cuda())
+
+
+CHEST_SHAPES = {
+    "64x16_comb8_td2": SlotShape(n_prb=3, n_symb=14, n_rx=64, n_layers=16, qm=6, dmrs_comb=8,
+                                 dmrs_td=2, dmrs_sym0=(2,), n_slots=2),
+    "16x4_2occ": SlotShape(n_prb=5, n_symb=14, n_rx=16, n_layers=4, qm=8, dmrs_comb=4, dmrs_td=1,
+                           dmrs_sym0=(2, 11), n_slots=2),
+    "12x3_odd": SlotShape(n_prb=7, n_symb=14, n_rx=12, n_layers=3, qm=4, dmrs_comb=2, dmrs_td=2,
+                          dmrs_sym0=(3,), n_slots=1),
+    "2x2": SlotShape(n_prb=4, n_symb=14, n_rx=2, n_layers=2, qm=2, dmrs_comb=2, dmrs_td=1,
+                     dmrs_sym0=(2,), n_slots=3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CHEST_SHAPES))
+@pytest.mark.parametrize("h_res", [0, 1])
+def test_fused_estimate_equals_estimate_of_decompressed_grid(name, h_res):
+    shape = CHEST_SHAPES[name]
+    say(f"chest_ls_bfp {name} h_res={h_res}")
+    words, pil, _ = _batch(shape, 300)
+    rx = ranphy.bfp_decompress(shape, words)
+    h_ref = ranphy.chest_ls(shape, rx, pil, h_res=h_res)
+    h = ranphy.chest_ls_bfp(shape, words, pil, h_res=h_res)
+    torch.cuda.synchronize()
+    assert torch.equal(h.view(torch.int64), h_ref.view(torch.int64))
+
+
+MFMA_SHAPES = {
+    "64x16": SlotShape(n_prb=3, n_symb=14, n_rx=64, n_layers=16, qm=6, dmrs_comb=8, dmrs_td=2,
+                       dmrs_sym0=(2,), n_slots=2),
+    "32x7_256qam": SlotShape(n_prb=4, n_symb=14, n_rx=32, n_layers=7, qm=8, dmrs_comb=4,
+                             dmrs_td=2, dmrs_sym0=(2,), n_slots=1),
+    "16x5_short": SlotShape(n_prb=2, n_symb=7, n_rx=16, n_layers=5, qm=4, dmrs_comb=4, dmrs_td=2,
+                            dmrs_sym0=(5,), n_slots=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MFMA_SHAPES))
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_fused_detector_equals_detector_on_decompressed_grid(name, prec):
+    """x, nv and LLRs bit for bit equal to ranphy_mmse_llr on the decompressed grid, every
+    precision; the channel is made near-collinear on some subcarriers so that the FP64 route
+    (which reads the samples again) runs too."""
+    shape = MFMA_SHAPES[name]
+    say(f"mmse_llr_bfp {name} prec={prec}")
+    words, pil, nvar = _batch(shape, 400)
+    rx = ranphy.bfp_decompress(shape, words)
+    h = ranphy.chest_ls(shape, rx, pil)
+    hv = h.view(shape.n_slots, shape.n_occ, -1, shape.n_rx, shape.n_layers)
+    hv[:, :, ::5, :, 1] = hv[:, :, ::5, :, 0] * (1 + 1e-6)  # ill-conditioned pilot rows
+    nvar = nvar * 1e-4
+    out = {}
+    for tag, fn, src in (("plain", ranphy.mmse_llr, rx), ("bfp", ranphy.mmse_llr_bfp, words)):
+        x = torch.empty(ranphy.buffer_floats(shape, ranphy.BUF_X) // 2, dtype=torch.complex64,
+                        device="cuda")
+        nv = torch.empty(ranphy.buffer_floats(shape, ranphy.BUF_NV), device="cuda")
+        llr = fn(shape, src, h, nvar, x=x, nv=nv, precision=prec)
+        out[tag] = (x, nv, llr)
+    torch.cuda.synchronize()
+    for a, b in zip(out["plain"], out["bfp"]):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_fused_chain_full_size_64x16():
+    """The compressed chain on the full 64 x 16 slot (273 PRB): estimate and LLRs from the
+    words equal the FP32 chain on the decompressed grid bit for bit, and at 30 dB the 9-bit
+    compression costs at most a few bit errors against the chain on the uncompressed grid."""
+    c = synth.CONFIGS["m"]
+    shape = c["shape"].with_slots(1)
+    say(f"bfp full chain {shape}")
+    d = synth.make_slot(shape, synth.rng_for(c["config_id"], 6, 0), c["scs_hz"], c["pdp"], 30.0)
+    rxh = np.ascontiguousarray(d["rx"]).reshape(-1)
+    words = ranphy.bfp_compress(shape, torch.from_numpy(rxh).cuda())
+    pil = torch.from_numpy(np.ascontiguousarray(d["pilots"])).cuda().reshape(-1)
+    nvar = torch.tensor([d["noise_var"]], dtype=torch.float32, device="cuda")
+    rx = ranphy.bfp_decompress(shape, words)
+    h_ref = ranphy.chest_ls(shape, rx, pil)
+    l_ref = ranphy.mmse_llr(shape, rx, h_ref, nvar)
+    h = ranphy.chest_ls_bfp(shape, words, pil)
+    llr = ranphy.mmse_llr_bfp(shape, words, h, nvar)
+    torch.cuda.synchronize()
+    assert torch.equal(h.view(torch.int64), h_ref.view(torch.int64))
+    assert torch.equal(llr.view(torch.int32), l_ref.view(torch.int32))
+    l_fp = ranphy.mmse_llr(shape, torch.from_numpy(rxh).cuda(),
+                           ranphy.chest_ls(shape, torch.from_numpy(rxh).cuda(), pil), nvar)
+    bits = d["bits"].reshape(-1) > 0
+    e_bfp = int(np.sum((llr.cpu().numpy() < 0) != bits))
+    e_fp = int(np.sum((l_fp.cpu().numpy() < 0) != bits))
+    say(f"  bit errors: BFP input {e_bfp}, FP32 input {e_fp} of {bits.size}")
+    assert e_bfp <= 1.1 * e_fp + 20
