@@ -739,6 +739,9 @@ def main():
             def fused_step(words):  # the decompression inside the estimator's and detector's loads
                 ranphy.chest_ls_bfp(shape, words, pil, h=h)
                 ranphy.mmse_llr_bfp(shape, words, h, nvar, llr=llr, precision=prec)
+        elif path == "receive":
+            def fused_step(words):  # the one-launch chain decoding the words where it loads them
+                ranphy.receive_bfp(shape, words, pil, nvar, llr=llr)
         out["pcie_h2d"] = h2d_rate(torch, b["rx"], ms_step, re, ranphy, shape, fused_step)
         out["slot_latency"] = slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec,
                                            path, scs_hz=synth.CONFIGS[args.workload]["scs_hz"])

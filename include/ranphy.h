@@ -297,6 +297,12 @@ RANPHY_API int ranphy_chest_ls_bfp(const ranphy_slot_desc* d, const uint32_t* pa
 RANPHY_API int ranphy_mmse_llr_bfp(const ranphy_slot_desc* d, const uint32_t* packed,
                                    const float* h, int h_res, const float* noise_var, float* x,
                                    float* nv, float* llr, int precision, void* stream);
+/* ranphy_receive with the received grid given as BFP words (packed: 4-byte aligned), every
+ * sample decoded where the one-launch chain loads it; antenna counts without a block width:
+ * RANPHY_ERR_UNSUPPORTED.  Bit for bit ranphy_receive on ranphy_bfp_decompress's output. */
+RANPHY_API int ranphy_receive_bfp(const ranphy_slot_desc* d, const uint32_t* packed,
+                                  const float* pilots, const float* noise_var, float* llr,
+                                  void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Many UEs of uneven allocations in one persistent launch (the scheduling and divergence

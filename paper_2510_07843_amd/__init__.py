@@ -37,7 +37,7 @@ EXPORTED_SYMBOLS = (
     "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
     "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run", "ranphy_receive",
     "ranphy_bfp_words", "ranphy_bfp_compress", "ranphy_bfp_decompress", "ranphy_chest_ls_bfp",
-    "ranphy_mmse_llr_bfp",
+    "ranphy_mmse_llr_bfp", "ranphy_receive_bfp",
 )
 
 
@@ -121,11 +121,13 @@ def lib() -> ctypes.CDLL:
         L.ranphy_bfp_decompress.argtypes = [D, P, P, P]
         L.ranphy_chest_ls_bfp.argtypes = [D, P, P, P, ctypes.c_int, P]
         L.ranphy_mmse_llr_bfp.argtypes = [D, P, P, ctypes.c_int, P, P, P, P, ctypes.c_int, P]
+        L.ranphy_receive_bfp.argtypes = [D, P, P, P, P, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
                   "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
                   "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_batch_plan",
                   "ranphy_batch_run", "ranphy_receive", "ranphy_bfp_compress",
-                  "ranphy_bfp_decompress", "ranphy_chest_ls_bfp", "ranphy_mmse_llr_bfp"):
+                  "ranphy_bfp_decompress", "ranphy_chest_ls_bfp", "ranphy_mmse_llr_bfp",
+                  "ranphy_receive_bfp"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -330,6 +332,21 @@ def mmse_llr_bfp(shape, packed: torch.Tensor, h: torch.Tensor, noise_var: torch.
     pl = _as_dev(llr, "llr", torch.float32, nl)
     _check("ranphy_mmse_llr_bfp", lib().ranphy_mmse_llr_bfp(
         ctypes.byref(d), *args, h_res, pn, px, pv, pl, precision, _stream(stream)))
+    return llr
+
+
+def receive_bfp(shape, packed: torch.Tensor, pilots: torch.Tensor, noise_var: torch.Tensor,
+                llr: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """receive with the received grid in block floating point form, decoded in the loads."""
+    d = desc_of(shape)
+    nl = buffer_floats(d, BUF_LLR)
+    if llr is None:
+        llr = torch.empty(nl, dtype=torch.float32, device=packed.device)
+    _check("ranphy_receive_bfp", lib().ranphy_receive_bfp(
+        ctypes.byref(d), _as_dev(packed, "packed", torch.int32, bfp_words(shape)),
+        _as_dev(pilots, "pilots", torch.complex64, buffer_floats(d, BUF_PILOTS)),
+        _as_dev(noise_var, "noise_var", torch.float32, buffer_floats(d, BUF_NOISE_VAR)),
+        _as_dev(llr, "llr", torch.float32, nl), _stream(stream)))
     return llr
 
 

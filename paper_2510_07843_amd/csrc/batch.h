@@ -110,7 +110,8 @@ int batch_tile_rows(const Geom& g, int k0, int nk);
 hipError_t launch_batch(void* plan, int blocks, hipStream_t s);
 // The one-launch chain for slots of one shape (ranphy_receive): tile width (0 if none fits).
 int receive_tile(const Geom& g, int tile_re);
-hipError_t launch_receive(const Geom& g, const float2* rx, const float2* pil, const float* nvar,
-                          float* llr, int nk, hipStream_t s);
+// rx: the complex64 grid, or with bfp its block floating point words (ranphy_bfp_compress).
+hipError_t launch_receive(const Geom& g, const float2* rx, bool bfp, const float2* pil,
+                          const float* nvar, float* llr, int nk, hipStream_t s);
 
 }  // namespace ranphy

@@ -33,6 +33,7 @@
 #include <float.h>
 
 #include "batch.h"
+#include "rx_load.h"
 #include "llr_math.h"
 
 namespace ranphy {
@@ -186,7 +187,7 @@ __device__ __forceinline__ void solve_emit(const Geom& g, float* __restrict__ ll
   }
 }
 
-template <int NL>
+template <int NL, int RXF>
 __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk,
                                             int jlo, int nj,
                             const float2* __restrict__ lds, const SymTab& tab) {
@@ -214,9 +215,9 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
     for (int i = 0; i < NP; ++i) G[i] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
-    const float2* __restrict__ yrow = u.rx + ((int64_t)s * g.n_sc + k) * NR;
+    const int64_t re = (int64_t)s * g.n_sc + k;
     for (int r = 0; r < NR; ++r) {
-      const float2 y = yrow[r];
+      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
       float2 hr[NL];
 #pragma unroll
       for (int p = 0; p < NL; ++p) {
@@ -249,7 +250,7 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
 // once; float4 (H0, D) per antenna and layer in pair[]) and A, S, C (in gram[]); each
 // resource element then blends its Gram, forms z = (H0 + t D)^H y from the staged pairs and
 // finishes as the other paths do.
-template <int NL>
+template <int NL, int RXF>
 __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g, int k0, int nk,
                                                  int jlo, int nj,
                                  const float2* __restrict__ rows, float4* __restrict__ pair,
@@ -318,11 +319,11 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
     }
 #pragma unroll
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
-    const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
+    const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
     const float4* q = pair + kk * PS;
 #pragma unroll 16
     for (int r = 0; r < NR; ++r) {
-      const float2 y = yrow[r];
+      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
 #pragma unroll
       for (int p = 0; p < NL; ++p) {
         const float4 v = q[r * NL + p];
@@ -435,7 +436,7 @@ __device__ __forceinline__ void factor_tile(const BatchUe& u, const Geom& g, int
 
 // One occasion, per resource element with the staged factor: matched filter, substitutions,
 // unbiasing, LLRs.
-template <int NL, class CAP>
+template <int NL, class CAP, int RXF>
 __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g, int k0, int nk,
                                                  int jlo,
                                  const float2* __restrict__ rows,
@@ -461,10 +462,10 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
     float2 z[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
-    const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
+    const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
 #pragma unroll 8
     for (int r = 0; r < NR; ++r) {
-      const float2 y = yrow[r];
+      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
 #pragma unroll
       for (int i = 0; i < NL; ++i)
         cmac_c(z[i], row_interp(rows, RS, NL, r0[i], r1[i], a[i], r, i), y);
@@ -514,7 +515,7 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
 // round trip per batch instead of one per estimate); indices are clamped into range and the
 // surplus discarded, so the loads need no branches.  T (the time cover length) is a template
 // parameter so that its loop unrolls.
-template <int T, int kStageBatch>
+template <int T, int kStageBatch, int RXF>
 __device__ __forceinline__ void stage_rows(const BatchUe& u, const Geom& g, int jlo, int nj,
                                            float2* __restrict__ rows) {
   const int C = g.comb, NR = g.n_rx, NL = g.n_layers, J = g.n_pilot, NSC = g.n_sc;
@@ -543,7 +544,7 @@ __device__ __forceinline__ void stage_rows(const BatchUe& u, const Geom& g, int 
       dst[b] = (o * nj + jj) * RS + r * NL + p;
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        yv[b][t] = u.rx[((int64_t)(s0 + t) * NSC + kc) * NR + r];
+        yv[b][t] = rx_at<RXF>(u.rx, (int64_t)(s0 + t) * NSC + kc, NR, r);
         qv[b][t] = u.pil[(((int64_t)o * T + t) * J + j) * NL + p];
       }
     }
@@ -563,7 +564,7 @@ __device__ __forceinline__ void stage_rows(const BatchUe& u, const Geom& g, int 
 // The LS estimate (Sec. III-B) of every pilot the tile k0 .. k0 + nk - 1 interpolates from,
 // every occasion, into rows[o][j - jlo][r][p] (rows of batch_row_stride values), and the
 // symbol tables into tab; returns jlo and the pilot count nj.  Ends with a barrier.
-template <int SB>
+template <int SB, int RXF>
 __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, int k0, int nk,
                                              float2* __restrict__ rows, SymTab& tab, int& jlo,
                                              int& nj) {
@@ -581,9 +582,9 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
   jlo = lo;
   nj = hi - lo + 1;
   if (T == 1)
-    stage_rows<1, SB>(u, g, jlo, nj, rows);
+    stage_rows<1, SB, RXF>(u, g, jlo, nj, rows);
   else
-    stage_rows<2, SB>(u, g, jlo, nj, rows);
+    stage_rows<2, SB, RXF>(u, g, jlo, nj, rows);
   if (threadIdx.x < g.n_dsym) {
     const int d = threadIdx.x;
     tab.dsym[d] = g.dsym[d];
@@ -600,7 +601,7 @@ __device__ __forceinline__ void stage_pilots(const BatchUe& u, const Geom& g, in
 // per resource element x~ = W y, the variance s2 d_l / mu_l from the staged d, and the LLRs.
 // Same quantities as detect_tile_fact, with the substitutions taken once per subcarrier and
 // antenna instead of once per resource element.
-template <int NL, class CAP>
+template <int NL, class CAP, int RXF>
 __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, int k0, int nk,
                                               int jlo, const float2* __restrict__ rows,
                                               const float2* __restrict__ fac,
@@ -653,11 +654,11 @@ __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, i
     float2 x[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) x[i] = make_float2(0.f, 0.f);
-    const float2* __restrict__ yrow = u.rx + ((int64_t)tab.dsym[d] * g.n_sc + k) * NR;
+    const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
     const float2* w = wf + kk * WS;
 #pragma unroll 8
     for (int r = 0; r < NR; ++r) {
-      const float2 y = yrow[r];
+      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
 #pragma unroll
       for (int l = 0; l < NL; ++l) {  // x_l += W[l][r] y_r
         const float2 c = w[r * NL + l];
@@ -684,51 +685,51 @@ __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, i
 }
 
 // One tile of nk subcarriers starting at k0: pilots staged, then the path for the DMRS layout.
-template <int NL, class CAP>
+template <int NL, class CAP, int RXF>
 __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, int k0, int nk,
                                              float2* rows, float2* fac, float* aux,
                                              SymTab& tab) {
   int jlo, nj;
-  stage_pilots<CAP::stage_batch>(u, g, k0, nk, rows, tab, jlo, nj);
+  stage_pilots<CAP::stage_batch, RXF>(u, g, k0, nk, rows, tab, jlo, nj);
   if (CAP::one_occ || g.n_occ == 1) {  // a one-occasion form is launched for those only
     factor_tile<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux);
     const int rs = batch_row_stride(g.n_rx, NL);
     if (batch_w_path(g, CAP::rows))  // the host's tile widths fit for such shapes
-      detect_tile_w<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux,
-                             rows + batch_pair_base(g.n_occ * nj, rs), tab);
+      detect_tile_w<NL, CAP, RXF>(u, g, k0, nk, jlo, rows, fac, aux,
+                                  rows + batch_pair_base(g.n_occ * nj, rs), tab);
     else
-      detect_tile_fact<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux, tab);
+      detect_tile_fact<NL, CAP, RXF>(u, g, k0, nk, jlo, rows, fac, aux, tab);
     return;
   }
   if constexpr (NL <= 4) {
     if (batch_pair_path(g, CAP::rows, CAP::fac)) {  // the host's tile widths fit
       float4* pair = reinterpret_cast<float4*>(
           rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
-      detect_tile_pair<NL>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
+      detect_tile_pair<NL, RXF>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
       return;
     }
   }
-  detect_tile<NL>(u, g, k0, nk, jlo, nj, rows, tab);
+  detect_tile<NL, RXF>(u, g, k0, nk, jlo, nj, rows, tab);
 }
 
-template <int MAXNL, int BLOCKS>
+template <int MAXNL, int BLOCKS, int RXF>
 __device__ __forceinline__ void process_any(const BatchUe& u, const Geom& g, int k0, int nk,
                                             float2* rows, float2* fac, float* aux, SymTab& tab) {
   using CAP = TileCap<MAXNL, BLOCKS>;
   switch (g.n_layers) {  // uniform over the block
-    case 1: process_tile<1, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 2: process_tile<2, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
-    case 3: process_tile<3, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 1: process_tile<1, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 2: process_tile<2, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
+    case 3: process_tile<3, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
     default:
       if constexpr (MAXNL == 4) {
-        process_tile<4, CAP>(u, g, k0, nk, rows, fac, aux, tab);
+        process_tile<4, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab);
       } else {
         switch (g.n_layers) {
-          case 4: process_tile<4, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
-          case 5: process_tile<5, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
-          case 6: process_tile<6, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
-          case 7: process_tile<7, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
-          default: process_tile<8, CAP>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 4: process_tile<4, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 5: process_tile<5, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 6: process_tile<6, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
+          case 7: process_tile<7, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
+          default: process_tile<8, CAP, RXF>(u, g, k0, nk, rows, fac, aux, tab); break;
         }
       }
       break;
@@ -760,7 +761,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
     const BatchItem item = items[it];
     const BatchUe& u = ues[item.ue];
     const Geom& g = u.g;  // read in place (a private copy indexed at run time would spill)
-    process_any<8, 3>(u, g, item.k0, item.nk, lds, fac, aux, tab);
+    process_any<8, 3, 0>(u, g, item.k0, item.nk, lds, fac, aux, tab);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -769,7 +770,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))
 // (slot, tile of nk subcarriers) stages the tile's pilot estimates and detects and demaps its
 // resource elements, as a work item of the multi-UE launch does.  BLOCKS blocks fit a CU
 // (LDS and registers).
-template <int MAXNL, int BLOCKS>
+// RXF = 1: rx holds the grid's block floating point words (rx_load.h), decoded where loaded.
+template <int MAXNL, int BLOCKS, int RXF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BLOCKS, 8)))
 receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__ pil,
                const float* __restrict__ nvar, float* __restrict__ llr, int nk) {
@@ -783,12 +785,19 @@ receive_kernel(Geom g, const float2* __restrict__ rx, const float2* __restrict__
   const int k0 = (blockIdx.x - slot * ntiles) * nk;
   BatchUe u;
   u.g = g;
-  u.rx = rx + (int64_t)slot * g.n_symb * g.n_sc * g.n_rx;
+  const int64_t slot_re = (int64_t)slot * g.n_symb * g.n_sc;
+  if constexpr (RXF == 0) {
+    u.rx = rx + slot_re * g.n_rx;
+  } else {  // words per resource element: blocks of 16 antennas (or all, below 16)
+    const int B = g.n_rx >= 16 ? 16 : g.n_rx;
+    const int64_t w_re = (int64_t)(g.n_rx / B) * (1 + (18 * B + 31) / 32);
+    u.rx = reinterpret_cast<const float2*>(reinterpret_cast<const unsigned*>(rx) + slot_re * w_re);
+  }
   u.pil = pil + (int64_t)slot * g.n_occ * g.td * g.n_pilot * g.n_layers;
   u.nv = nvar + slot;
   u.llr = llr + (int64_t)slot * g.n_dsym * g.n_sc * g.n_layers * g.qm;
   const int n = min(nk, g.n_sc - k0);
-  process_any<MAXNL, BLOCKS>(u, g, k0, n, lds, fac, aux, tab);
+  process_any<MAXNL, BLOCKS, RXF>(u, g, k0, n, lds, fac, aux, tab);
 }
 
 }  // namespace
@@ -836,21 +845,33 @@ int receive_tile(const Geom& g, int tile_re) {
   return 0;
 }
 
-hipError_t launch_receive(const Geom& g, const float2* rx, const float2* pil, const float* nvar,
-                          float* llr, int nk, hipStream_t s) {
-  const int64_t ntiles = (g.n_sc + nk - 1) / nk;
-  const dim3 grid((unsigned)(g.n_slots * ntiles));
+template <int RXF>
+void launch_receive_rxf(const Geom& g, dim3 grid, const float2* rx, const float2* pil,
+                        const float* nvar, float* llr, int nk, hipStream_t s) {
   switch (receive_form(g)) {
     case 2:
-      hipLaunchKernelGGL((receive_kernel<4, 5>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+      hipLaunchKernelGGL((receive_kernel<4, 5, RXF>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr,
+                         nk);
       break;
     case 1:
-      hipLaunchKernelGGL((receive_kernel<4, 4>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+      hipLaunchKernelGGL((receive_kernel<4, 4, RXF>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr,
+                         nk);
       break;
     default:
-      hipLaunchKernelGGL((receive_kernel<8, 3>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr, nk);
+      hipLaunchKernelGGL((receive_kernel<8, 3, RXF>), grid, dim3(256), 0, s, g, rx, pil, nvar, llr,
+                         nk);
       break;
   }
+}
+
+hipError_t launch_receive(const Geom& g, const float2* rx, bool bfp, const float2* pil,
+                          const float* nvar, float* llr, int nk, hipStream_t s) {
+  const int64_t ntiles = (g.n_sc + nk - 1) / nk;
+  const dim3 grid((unsigned)(g.n_slots * ntiles));
+  if (bfp)
+    launch_receive_rxf<1>(g, grid, rx, pil, nvar, llr, nk, s);
+  else
+    launch_receive_rxf<0>(g, grid, rx, pil, nvar, llr, nk, s);
   return hipGetLastError();
 }
 

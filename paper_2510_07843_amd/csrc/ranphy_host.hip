@@ -371,8 +371,26 @@ int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilo
   const int nk = ranphy::receive_tile(g, 256);
   if (nk < 1) return RANPHY_ERR_UNSUPPORTED;
   return ranphy::status_of(ranphy::launch_receive(
-      g, reinterpret_cast<const float2*>(rx), reinterpret_cast<const float2*>(pilots), noise_var,
-      llr, nk, static_cast<hipStream_t>(stream)));
+      g, reinterpret_cast<const float2*>(rx), false, reinterpret_cast<const float2*>(pilots),
+      noise_var, llr, nk, static_cast<hipStream_t>(stream)));
+}
+
+int ranphy_receive_bfp(const ranphy_slot_desc* d, const uint32_t* packed, const float* pilots,
+                       const float* noise_var, float* llr, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (g.n_layers > ranphy::kBatchMaxLayers || ranphy::bfp_block(g.n_rx) == 0)
+    return RANPHY_ERR_UNSUPPORTED;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (packed == nullptr || ((uintptr_t)packed & 3u) || !ranphy::aligned8(pilots) ||
+      !ranphy::aligned8(llr) || noise_var == nullptr || ((uintptr_t)noise_var & 3u))
+    return RANPHY_ERR_INVALID;
+  const int nk = ranphy::receive_tile(g, 256);
+  if (nk < 1) return RANPHY_ERR_UNSUPPORTED;
+  return ranphy::status_of(ranphy::launch_receive(
+      g, reinterpret_cast<const float2*>(packed), true, reinterpret_cast<const float2*>(pilots),
+      noise_var, llr, nk, static_cast<hipStream_t>(stream)));
 }
 
 // ---- block floating point compression of the received grid --------------------------------

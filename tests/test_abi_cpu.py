@@ -299,3 +299,10 @@ def test_fused_bfp_validation(L):
     assert L.ranphy_mmse_llr_bfp(ctypes.byref(m0), P(0), P(0), 0, P(0), None, None, P(0), 0,
                                  None) == 0
     assert L.ranphy_chest_ls_bfp(ctypes.byref(m0), P(0), P(0), P(0), 0, None) == 0
+    # the one-launch chain: up to 8 layers, antenna counts with a block width
+    assert L.ranphy_receive_bfp(ctypes.byref(d), P(0x1002), P(8), P(8), P(8), None) == -1
+    assert L.ranphy_receive_bfp(ctypes.byref(d), P(8), P(8), P(8), P(0x1004), None) == -1
+    assert L.ranphy_receive_bfp(ctypes.byref(_desc(n_rx=20, n_layers=4)), P(8), P(8), P(8), P(8),
+                                None) == -2
+    assert L.ranphy_receive_bfp(ctypes.byref(m), P(8), P(8), P(8), P(8), None) == -2  # 16 layers
+    assert L.ranphy_receive_bfp(ctypes.byref(_desc(n_slots=0)), P(0), P(0), P(0), P(0), None) == 0

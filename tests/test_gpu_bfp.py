@@ -284,3 +284,49 @@ def test_fused_chain_full_size_64x16():
     e_fp = int(np.sum((l_fp.cpu().numpy() < 0) != bits))
     say(f"  bit errors: BFP input {e_bfp}, FP32 input {e_fp} of {bits.size}")
     assert e_bfp <= 1.1 * e_fp + 20
+
+
+RECEIVE_SHAPES = {
+    "4x2_qpsk": SlotShape(n_prb=6, n_symb=14, n_rx=4, n_layers=2, qm=2, dmrs_comb=2, dmrs_td=1,
+                          dmrs_sym0=(2,), n_slots=2),
+    "16x4_2occ_256qam": SlotShape(n_prb=9, n_symb=14, n_rx=16, n_layers=4, qm=8, dmrs_comb=4,
+                                  dmrs_td=1, dmrs_sym0=(2, 11), n_slots=2),
+    "8x8_td2": SlotShape(n_prb=5, n_symb=14, n_rx=8, n_layers=8, qm=2, dmrs_comb=4, dmrs_td=2,
+                         dmrs_sym0=(2,), n_slots=2),
+    "12x3_3occ": SlotShape(n_prb=7, n_symb=14, n_rx=12, n_layers=3, qm=6, dmrs_comb=4,
+                           dmrs_td=1, dmrs_sym0=(2, 6, 10), n_slots=1),
+    "32x6_2occ": SlotShape(n_prb=4, n_symb=14, n_rx=32, n_layers=6, qm=4, dmrs_comb=4, dmrs_td=2,
+                           dmrs_sym0=(2, 10), n_slots=1),
+    "1x1": SlotShape(n_prb=3, n_symb=14, n_rx=1, n_layers=1, qm=4, dmrs_comb=2, dmrs_td=1,
+                     dmrs_sym0=(3,), n_slots=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(RECEIVE_SHAPES))
+def test_fused_one_launch_chain_equals_chain_on_decompressed_grid(name):
+    """ranphy_receive_bfp: every path of the one-launch chain (per RE, channel pairs, factor,
+    filter) reading the words gives ranphy_receive's LLRs on the decompressed grid bit for bit."""
+    shape = RECEIVE_SHAPES[name]
+    say(f"receive_bfp {name}")
+    words, pil, nvar = _batch(shape, 500)
+    rx = ranphy.bfp_decompress(shape, words)
+    ref = ranphy.receive(shape, rx, pil, nvar)
+    llr = ranphy.receive_bfp(shape, words, pil, nvar)
+    torch.cuda.synchronize()
+    assert torch.equal(llr.view(torch.int32), ref.view(torch.int32))
+
+
+def test_fused_one_launch_chain_full_size_16x4():
+    c = synth.CONFIGS["c2"]
+    shape = c["shape"].with_slots(2)
+    say(f"receive_bfp full size {shape}")
+    ds = [synth.make_slot(shape.with_slots(1), synth.rng_for(c["config_id"], i, 0), c["scs_hz"],
+                          c["pdp"], c["snr_db"][i]) for i in range(2)]
+    rx = torch.from_numpy(np.ascontiguousarray(np.stack([d["rx"] for d in ds]))).cuda().reshape(-1)
+    pil = torch.from_numpy(np.ascontiguousarray(np.stack([d["pilots"] for d in ds]))).cuda().reshape(-1)
+    nvar = torch.tensor([d["noise_var"] for d in ds], dtype=torch.float32, device="cuda")
+    words = ranphy.bfp_compress(shape, rx)
+    ref = ranphy.receive(shape, ranphy.bfp_decompress(shape, words), pil, nvar)
+    llr = ranphy.receive_bfp(shape, words, pil, nvar)
+    torch.cuda.synchronize()
+    assert torch.equal(llr.view(torch.int32), ref.view(torch.int32))
