@@ -87,7 +87,7 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
-                "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+                "`python paper_2510_07843_amd/build.py` (hipcc, gfx950)")
         L = ctypes.CDLL(LIB_PATH)
         D = ctypes.POINTER(SlotDesc)
         P = ctypes.c_void_p

@@ -115,7 +115,7 @@ def sinr_db(x_hat: np.ndarray, x: np.ndarray) -> float:
 
 def choose_gate_sinr(params: torch.Tensor, shape, rx: torch.Tensor, pilots: torch.Tensor,
                      noise_var: torch.Tensor, x_true: np.ndarray, snr_db: Sequence[float]) -> Dict:
-    """The noise-variance gate judged on what detection sees: per SNR point of full validation
+    """The noise-variance gate chosen by what detection sees: per SNR point of full validation
     slots, the post-equalisation SINR of the FP32 detector with the plain and with the refined
     (ungated) estimate against the transmitted symbols; refine up to the highest SNR point at
     or below which every point gains, keep the plain estimate above it."""

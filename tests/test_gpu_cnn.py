@@ -229,7 +229,7 @@ def test_trained_denoiser_beats_plain_estimate():
     # 16 Rx x 16 layers over 273 PRB (comb 8, double-symbol cover: 410 pilots per port), the
     # 64 x 16 workload's pilot grid.  Train on the GPU (300 Adam steps, 4 slots of 256 images
     # a step) on 160 slots drawn with delay spread 30..300 ns, Doppler 0..500 Hz and SNR
-    # 0..30 dB; choose the noise-variance gate on validation slots; then judge the NMSE of the
+    # 0..30 dB; choose the noise-variance gate on validation slots; then measure the NMSE of the
     # pilot-resolution estimate on held-out test slots against the plain LS estimate.
     from paper_2510_07843_amd import denoise
     base = synth.SlotShape(273, 14, 16, 16, 6, 8, 2, (2,), 1)
