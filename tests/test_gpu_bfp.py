@@ -330,3 +330,36 @@ def test_fused_one_launch_chain_full_size_16x4():
     llr = ranphy.receive_bfp(shape, words, pil, nvar)
     torch.cuda.synchronize()
     assert torch.equal(llr.view(torch.int32), ref.view(torch.int32))
+
+
+def test_launch_chunking_past_2_26_blocks():
+    """A grid of more than 2^26 blocks (368 slots of the 64-antenna, 273-PRB shape: 67.4 M
+    blocks, 8.6 GB of samples) takes two launches per direction: every block must satisfy
+    the error bound and exponent minimality, and blocks on both sides of the chunk boundary
+    must match the oracle bit for bit."""
+    shape = synth.CONFIGS["m"]["shape"].with_slots(368)
+    n = ranphy.buffer_floats(shape, ranphy.BUF_RX) // 2
+    n_blocks = n // 16
+    assert n_blocks > (1 << 26)
+    say(f"bfp chunking: {n_blocks} blocks")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    rx = torch.randn(n, dtype=torch.complex64, device="cuda", generator=g)
+    words = ranphy.bfp_compress(shape, rx)
+    back = ranphy.bfp_decompress(shape, words)
+    torch.cuda.synchronize()
+    v = torch.view_as_real(rx).reshape(n_blocks, 32)
+    vb = torch.view_as_real(back).reshape(n_blocks, 32)
+    e = words.view(n_blocks, 10)[:, 0].to(torch.float64)
+    step = torch.pow(2.0, e).to(torch.float64)
+    err = (vb.double() - v.double()).abs().amax(dim=1)
+    assert bool((err <= 0.5 * step).all())
+    peak = v.double().abs().amax(dim=1)
+    assert bool((peak <= 255.0 * step).all()) and bool((peak > 127.5 * step).all())
+    del v, vb, err, peak, step, e
+    lo, hi = (1 << 26) - 64, (1 << 26) + 64
+    sub = rx.view(n_blocks, 16)[lo:hi].cpu().numpy().reshape(-1)
+    wr = bref.compress(sub, 16)
+    assert np.array_equal(words.view(n_blocks, 10)[lo:hi].cpu().numpy().view(np.uint32).reshape(-1), wr)
+    assert np.array_equal(bits(back.view(n_blocks, 16)[lo:hi].cpu().numpy().reshape(-1)),
+                          bits(bref.decompress(wr, 16, sub.size)))

@@ -158,6 +158,29 @@ def test_one_row_forward_in_place():
     assert torch.equal(y[g1], x[g1])  # below the gate
 
 
+def test_one_row_inference_past_65535_groups():
+    """More groups than one launch's grid rows (the input normalisation goes in chunks of
+    65 535 groups): 70 000 one-pixel groups of 4 images, with a gate, against the same
+    groups run in two halves."""
+    rows, cols, nimg, ngrp = 1, 1, 4, 70000
+    p = torch.from_numpy(pack(net_params(11))).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = torch.randn(ngrp * nimg * 2, device="cuda", generator=g)
+    nv = torch.rand(ngrp, device="cuda", generator=g) + 0.01
+    full = ranphy.cnn_forward(p, x, rows, cols, nimg, ngrp, noise_var=nv, min_noise_var=0.5)
+    half = ngrp // 2
+    a = ranphy.cnn_forward(p, x[:half * nimg * 2], rows, cols, nimg, half, noise_var=nv[:half],
+                           min_noise_var=0.5)
+    b = ranphy.cnn_forward(p, x[half * nimg * 2:], rows, cols, nimg, ngrp - half,
+                           noise_var=nv[half:], min_noise_var=0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(full, torch.cat([a, b]))
+    kept = (nv < 0.5).repeat_interleave(nimg * 2)
+    assert torch.equal(full[kept], x[kept])  # below the gate: the input, exactly
+    assert not torch.equal(full[~kept], x[~kept])
+
+
 def test_noise_normalised_forward_and_gradients():
     # With per-group noise variances the network sees x / sigma and refines x into x + sigma y;
     # the loss compares x / sigma + y with target / sigma.  The oracle runs on the normalised
