@@ -213,7 +213,8 @@ RANPHY_API int64_t ranphy_cnn_param_count(void);
 RANPHY_API int64_t ranphy_cnn_workspace_bytes(int rows, int cols, int n_img, int n_groups,
                                               int train);
 /* out = x + sigma y (x + y without noise variances); groups whose noise variance is below
- * min_noise_var, or not positive, keep out = x.  out may alias x. */
+ * min_noise_var, or not positive, keep out = x.  out may be x itself (in place); it must not
+ * otherwise overlap x. */
 RANPHY_API int ranphy_cnn_forward(const float* params, const float* x, const float* noise_var,
                                   float min_noise_var, float* out, int rows, int cols,
                                   int n_img, int n_groups, void* workspace,
@@ -230,7 +231,7 @@ RANPHY_API int ranphy_cnn_grad(const float* params, const float* x, const float*
 RANPHY_API int ranphy_cnn_adam(float* params, const float* grad, float* m, float* v, int step,
                                float lr, void* stream);
 /* The network applied to a pilot-resolution estimate (ranphy_chest_ls with RANPHY_H_PILOT),
- * h_out in the same layout (may alias h_in).  Slots whose noise variance noise_var[slot]
+ * h_out in the same layout (may be h_in itself, not otherwise overlap it).  Slots whose noise variance noise_var[slot]
  * (device, as for ranphy_mmse_detect; may be NULL: every slot refined) is below
  * min_noise_var keep the plain estimate: above the SNR where validation shows the refinement
  * no longer helps, plain interpolation of the LS estimate is the better one.  Processed in as
@@ -274,6 +275,7 @@ RANPHY_API int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const 
  * ranphy_bfp_compress: rx (device, 8-byte aligned) -> packed (device, 4-byte aligned,
  *   ranphy_bfp_words(d) words).  Values must be finite.
  * ranphy_bfp_decompress: packed -> rx; rx then holds exactly what the receive calls expect.
+ * The words and the samples must not overlap.
  * Both are asynchronous on `stream`; host validation as for the other calls.
  */
 RANPHY_API int64_t ranphy_bfp_words(const ranphy_slot_desc* d);
