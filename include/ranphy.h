@@ -233,9 +233,9 @@ RANPHY_API int ranphy_cnn_adam(float* params, const float* grad, float* m, float
 /* The network applied to a pilot-resolution estimate (ranphy_chest_ls with RANPHY_H_PILOT),
  * h_out in the same layout (it may be h_in itself, but must not otherwise overlap it).  Slots
  * whose noise variance noise_var[slot] (device, as for ranphy_mmse_detect; may be NULL: every
- * slot refined) is below
- * min_noise_var keep the plain estimate: above the SNR where validation shows the refinement
- * no longer helps, plain interpolation of the LS estimate is the better one.  Processed in as
+ * slot refined) is below min_noise_var keep the plain estimate: above the SNR where validation
+ * shows the refinement no longer helps, plain interpolation of the LS estimate is the better
+ * one.  Processed in as
  * many slots per pass as the workspace holds (at least ranphy_cnn_workspace_bytes(n_occ,
  * ceil(n_sc / C), n_rx * n_layers, 1, 0) bytes). */
 RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params,
