@@ -575,8 +575,8 @@ def main():
         print(json.dumps({"copy_ref_bytes_each_way": n * 4, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (see the "
-                                   "sharding design: slots, cells and UEs are independent)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (slots, "
+                                   "cells and UEs are independent, so the work shards by slot)"}))
         sys.exit(2)
 
     import torch
