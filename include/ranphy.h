@@ -252,7 +252,10 @@ RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params
  * resolution) -> ranphy_mmse_detect -> ranphy_llr_demap up to rounding order.
  *   rx, pilots, noise_var as for ranphy_chest_ls / ranphy_mmse_detect;
  *   llr out [slot][dsym][sc][layer][qm] float.
- * More than 8 layers: RANPHY_ERR_UNSUPPORTED (use the three calls or ranphy_mmse_llr).
+ * More than 8 layers run on the matrix-core detector, each block forming the pilot estimates
+ * it needs itself with ranphy_chest_ls's arithmetic, so the LLRs equal ranphy_chest_ls ->
+ * ranphy_mmse_llr bit for bit; this needs that detector's shapes (one DMRS occasion, n_rx a
+ * multiple of 16, rx and llr 16-byte aligned), else RANPHY_ERR_UNSUPPORTED.
  */
 RANPHY_API int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilots,
                               const float* noise_var, float* llr, void* stream);

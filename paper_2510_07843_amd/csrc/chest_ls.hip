@@ -17,18 +17,14 @@ __device__ __forceinline__ float2 ls_at(const Geom& g, const float2* __restrict_
                                         const float2* __restrict__ pil, int64_t slot, int o,
                                         int j, int r, int p) {
   const int k = (p & (g.comb - 1)) + g.comb * j;
-  float2 acc = make_float2(0.f, 0.f);
+  float2 y[T], q[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int s = g.sym0[o] + t;
-    const float2 y = rx_at<RXF>(rx, (slot * g.n_symb + s) * g.n_sc + k, g.n_rx, r);
-    const float2 q = pil[(((slot * g.n_occ + o) * T + t) * g.n_pilot + j) * g.n_layers + p];
-    const float2 m = cmulc(q, y);  // y * conj(q)
-    acc.x += m.x;
-    acc.y += m.y;
+    y[t] = rx_at<RXF>(rx, (slot * g.n_symb + s) * g.n_sc + k, g.n_rx, r);
+    q[t] = pil[(((slot * g.n_occ + o) * T + t) * g.n_pilot + j) * g.n_layers + p];
   }
-  const float inv = 1.f / (float)T;
-  return make_float2(acc.x * inv, acc.y * inv);
+  return ls_pilot<T>(q, y);
 }
 
 // Pilot resolution: one block per (slot, occasion, pilot index j).  The C subcarriers
@@ -64,21 +60,21 @@ __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* 
   }
   __syncthreads();
   float2* __restrict__ dst = h + ((int64_t)so * g.n_pilot + j) * NR * NL;
-  const float inv = 1.f / (float)T;
   for (int e = threadIdx.x; e < NR * NL; e += 256) {
     const int r = e / NL;
     const int p = e - r * NL;
     const int c = p & (C - 1);
-    float2 acc = make_float2(0.f, 0.f);
+    float2 v = make_float2(0.f, 0.f);
     if (C * j + c < g.n_sc) {
+      float2 q[T], y[T];
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        const float2 m = cmulc(ps[t * NL + p], ys[(t * C + c) * (NR + 1) + r]);  // y conj(q)
-        acc.x += m.x;
-        acc.y += m.y;
+        q[t] = ps[t * NL + p];
+        y[t] = ys[(t * C + c) * (NR + 1) + r];
       }
+      v = ls_pilot<T>(q, y);
     }
-    dst[e] = make_float2(acc.x * inv, acc.y * inv);
+    dst[e] = v;
   }
 }
 
@@ -128,7 +124,6 @@ __global__ void __launch_bounds__(256) chest_run_kernel(Geom g, const float2* __
   }
   __syncthreads();
   float2* __restrict__ dst = h + ((int64_t)so * g.n_pilot + j0) * NR * NL;
-  const float inv = 1.f / (float)T;
   for (int e = threadIdx.x; e < nj * NR * NL; e += 256) {
     const int jj = e / (NR * NL);
     const int rem = e - jj * (NR * NL);
@@ -136,16 +131,17 @@ __global__ void __launch_bounds__(256) chest_run_kernel(Geom g, const float2* __
     const int p = rem - r * NL;
     const int c = p & (C - 1);
     const int kk = C * jj + c;
-    float2 acc = make_float2(0.f, 0.f);
+    float2 v = make_float2(0.f, 0.f);
     if (C * j0 + kk < g.n_sc) {
+      float2 q[T], y[T];
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        const float2 m = cmulc(ps[(t * jb + jj) * NL + p], ys[(t * C * jb + kk) * pitch + r]);
-        acc.x += m.x;  // y conj(q)
-        acc.y += m.y;
+        q[t] = ps[(t * jb + jj) * NL + p];
+        y[t] = ys[(t * C * jb + kk) * pitch + r];
       }
+      v = ls_pilot<T>(q, y);
     }
-    dst[e] = make_float2(acc.x * inv, acc.y * inv);
+    dst[e] = v;
   }
 }
 

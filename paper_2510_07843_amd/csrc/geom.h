@@ -66,6 +66,21 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
   return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// LS estimate at one pilot from its T received samples y[t] and pilot values q[t]:
+// (1/T) sum_t y_t conj(q_t), every rounding step written out (fused multiply-adds in a fixed
+// order, then the exact scaling by 1/T) so that every kernel forming it gets the same bits.
+template <int T>
+__device__ __forceinline__ float2 ls_pilot(const float2 (&q)[T], const float2 (&y)[T]) {
+  float re = 0.f, im = 0.f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    re = fmaf(q[t].x, y[t].x, fmaf(q[t].y, y[t].y, re));
+    im = fmaf(q[t].x, y[t].y, fmaf(-q[t].y, y[t].x, im));
+  }
+  constexpr float inv = 1.f / (float)T;
+  return make_float2(re * inv, im * inv);
+}
+
 // Kernel launchers (one translation unit each).  They return a hipError_t.
 // rx: the complex64 grid, or with bfp its block floating point words (ranphy_bfp_compress).
 hipError_t launch_chest_ls(const Geom& g, const float2* rx, bool bfp, const float2* pilots,

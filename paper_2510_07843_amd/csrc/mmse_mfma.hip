@@ -31,6 +31,10 @@
 // decoded in registers just before the matched filter; the decoded values equal those of
 // the separate decompression kernel bit for bit, so the results do too.
 //
+// With LSF = 1 (pilot resolution, the one-launch chain) the block estimates its pilot rows
+// itself from the received DMRS samples and the pilots, with the same arithmetic as the LS
+// kernels (ls_pilot), so the whole chain gives the bits of ranphy_chest_ls -> this detector.
+//
 // MFMA operand layouts (16x16x4, single block), lane l = 16 q + c:
 //   A[i][kk] <- lane (i + 16 kk);  B[kk][j] <- lane (j + 16 kk);  D[i][j] -> lane (j + 16 (i/4)),
 //   register i % 4.  The K index of step s is mapped to receive antenna 16 q + s, so that
@@ -41,6 +45,7 @@
 
 #include "geom.h"
 #include "llr_math.h"
+#include "rx_load.h"
 
 namespace ranphy {
 namespace {
@@ -518,14 +523,15 @@ __device__ __forceinline__ void emit_llr(float* __restrict__ llr, float* stage, 
   }
 }
 
-template <int HRES, int NL, int PREC, int RXF>
+template <int HRES, int NL, int PREC, int RXF, int LSF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
+                                                        const float2* __restrict__ pil,
                                                         const float* __restrict__ nvar,
                                                         float2* __restrict__ x,
                                                         float* __restrict__ nv,
                                                         float* __restrict__ llr) {
-  __shared__ float lds_t[4][16 * 17];
+  __shared__ __attribute__((aligned(16))) float lds_t[4][16 * 17];
   // Channel rows staged per block: full resolution needs the 4 subcarriers' rows; at pilot
   // resolution 9..16 layers imply comb 8 (Nl <= C T), whose 4 subcarriers span at most 3
   // pilot rows, and 5..8 layers at most 4 (comb 4).
@@ -568,13 +574,66 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     jlo = k0;
     nrow = 4;
   }
-  {
+  if constexpr (LSF == 0) {
     const int row_f4 = (NR * NL) >> 1;
     const int64_t row0 = (int64_t)slot * (HRES == 0 ? g.n_pilot : g.n_sc) + jlo;
     const float4* __restrict__ src = reinterpret_cast<const float4*>(h + row0 * NR * NL);
     float4* __restrict__ dst = reinterpret_cast<float4*>(lds_h);
     const int n4 = nrow * row_f4;
     for (int f = threadIdx.x; f < n4; f += 256) dst[f] = src[f];
+  } else {
+    // Rows jlo .. jlo + nrow - 1 estimated here.  The block's pilots go to LDS first (into
+    // lds_t, free until the Gram transpose); thread (group gg, antenna r) then issues all of
+    // its received-sample loads (the T DMRS samples of subcarrier C j + c, at most kItems
+    // groups) before it forms, for every port on that comb offset, the estimate ranphy_chest_ls
+    // would write (zero past the band edge).  More than 8 layers imply comb 8 and T = 2, so a
+    // thread has at most nrow C NR / 256 <= 2 kRows groups.
+    const int C = g.comb, T = g.td;
+    const int npq = nrow * T * NL;
+    float2* __restrict__ pst = reinterpret_cast<float2*>(&lds_t[0][0]);
+    for (int e = threadIdx.x; e < npq; e += 256) {
+      const int row = e / (T * NL), rem = e - row * (T * NL);
+      const int t = rem / NL, p = rem - t * NL;
+      pst[e] = pil[(((int64_t)slot * T + t) * g.n_pilot + jlo + row) * NL + p];
+    }
+    constexpr int kItems = 2 * kRows;
+    // gs whole groups of NR threads (NR <= 64); with 48 antennas the last 16 threads idle
+    const int r = threadIdx.x % NR, gs = 256 / NR, g0 = threadIdx.x / NR;
+    const int64_t sym_re = ((int64_t)slot * g.n_symb + g.sym0[0]) * g.n_sc;
+    float2 ys[kItems][2];
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int gg = g0 + it * gs;
+      ys[it][0] = ys[it][1] = make_float2(0.f, 0.f);
+      if (g0 < gs && gg < nrow * C) {
+        const int kc = min(C * (jlo + (gg >> g.comb_log2)) + (gg & (C - 1)), g.n_sc - 1);
+        ys[it][0] = rx_at<RXF>(rx, sym_re + kc, NR, r);
+        if (T == 2) ys[it][1] = rx_at<RXF>(rx, sym_re + g.n_sc + kc, NR, r);
+      }
+    }
+    __syncthreads();  // the pilots are staged
+#pragma unroll
+    for (int it = 0; it < kItems; ++it) {
+      const int gg = g0 + it * gs;
+      if (g0 < gs && gg < nrow * C) {
+        const int row = gg >> g.comb_log2, cc = gg & (C - 1);
+        const bool in = C * (jlo + row) + cc < g.n_sc;
+        for (int p = cc; p < NL; p += C) {
+          float2 v = make_float2(0.f, 0.f);
+          if (in) {
+            const float2* pq = pst + row * T * NL + p;
+            if (T == 1) {
+              const float2 q1[1] = {pq[0]}, y1[1] = {ys[it][0]};
+              v = ls_pilot<1>(q1, y1);
+            } else {
+              const float2 q2[2] = {pq[0], pq[NL]}, y2[2] = {ys[it][0], ys[it][1]};
+              v = ls_pilot<2>(q2, y2);
+            }
+          }
+          lds_h[(row * NR + r) * NL + p] = v;
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -806,41 +865,56 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   }
 }
 
+// pil != NULL: the pilot-resolution estimate is formed inside the detector (LSF = 1).
 template <int HRES, int NL, int PREC>
 void launch_one(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
-                const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
+                const float2* pil, const float* nvar, float2* x, float* nv, float* llr,
+                hipStream_t s) {
+  if constexpr (HRES == 0) {
+    if (pil != nullptr) {
+      if (bfp)
+        hipLaunchKernelGGL((mmse_mfma_kernel<0, NL, PREC, 1, 1>), grid, dim3(256), 0, s, g, rx,
+                           h, pil, nvar, x, nv, llr);
+      else
+        hipLaunchKernelGGL((mmse_mfma_kernel<0, NL, PREC, 0, 1>), grid, dim3(256), 0, s, g, rx,
+                           h, pil, nvar, x, nv, llr);
+      return;
+    }
+  }
   if (bfp)
-    hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC, 1>), grid, dim3(256), 0, s, g, rx, h,
-                       nvar, x, nv, llr);
+    hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC, 1, 0>), grid, dim3(256), 0, s, g, rx, h,
+                       pil, nvar, x, nv, llr);
   else
-    hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC, 0>), grid, dim3(256), 0, s, g, rx, h,
-                       nvar, x, nv, llr);
+    hipLaunchKernelGGL((mmse_mfma_kernel<HRES, NL, PREC, 0, 0>), grid, dim3(256), 0, s, g, rx, h,
+                       pil, nvar, x, nv, llr);
 }
 
 template <int HRES, int PREC>
 void launch_nl(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
-               const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
+               const float2* pil, const float* nvar, float2* x, float* nv, float* llr,
+               hipStream_t s) {
   switch (g.n_layers) {
-    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
-    default: launch_one<HRES, 16, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s); break;
+    case 5: launch_one<HRES, 5, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 6: launch_one<HRES, 6, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 7: launch_one<HRES, 7, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 8: launch_one<HRES, 8, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 9: launch_one<HRES, 9, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 10: launch_one<HRES, 10, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 11: launch_one<HRES, 11, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 12: launch_one<HRES, 12, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 13: launch_one<HRES, 13, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 14: launch_one<HRES, 14, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    case 15: launch_one<HRES, 15, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
+    default: launch_one<HRES, 16, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s); break;
   }
 }
 
 template <int PREC>
 void launch_prec(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
-                 int h_res, const float* nvar, float2* x, float* nv, float* llr, hipStream_t s) {
-  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s);
-  else launch_nl<1, PREC>(g, grid, rx, bfp, h, nvar, x, nv, llr, s);
+                 const float2* pil, int h_res, const float* nvar, float2* x, float* nv,
+                 float* llr, hipStream_t s) {
+  if (h_res == 0) launch_nl<0, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s);
+  else launch_nl<1, PREC>(g, grid, rx, bfp, h, pil, nvar, x, nv, llr, s);
 }
 
 }  // namespace
@@ -856,15 +930,15 @@ bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void
 }
 
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, bool bfp, const float2* h,
-                            int h_res, const float* nvar, float2* x, float* nv, float* llr,
-                            int prec, hipStream_t s) {
+                            const float2* pil, int h_res, const float* nvar, float2* x,
+                            float* nv, float* llr, int prec, hipStream_t s) {
   const int64_t waves = (int64_t)g.n_slots * g.n_sc;
   const int64_t blocks = (waves + 3) / 4;
   const dim3 grid((unsigned)((blocks + kXcds - 1) / kXcds * kXcds));
   switch (prec) {
-    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, bfp, h, h_res, nvar, x, nv, llr, s); break;
-    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, bfp, h, h_res, nvar, x, nv, llr, s); break;
-    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, bfp, h, h_res, nvar, x, nv, llr, s); break;
+    case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
+    case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
+    case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -17,9 +17,11 @@
 namespace ranphy {
 
 // rx: the complex64 grid, or with bfp its block floating point words (16-antenna blocks).
+// pil: NULL to read h, or the pilots, the pilot-resolution estimate then being formed in the
+// kernel (h unused, h_res pilot).
 hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, bool bfp, const float2* h,
-                            int h_res, const float* noise_var, float2* x, float* nv, float* llr,
-                            int prec, hipStream_t s);
+                            const float2* pil, int h_res, const float* noise_var, float2* x,
+                            float* nv, float* llr, int prec, hipStream_t s);
 bool mmse_mfma_eligible(const Geom& g, const void* rx, const void* h, const void* x,
                         const void* nv, const void* llr);
 
@@ -187,8 +189,8 @@ int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx, const fl
   if (precision != RANPHY_PREC_FP32 && !mfma) return RANPHY_ERR_UNSUPPORTED;
   if (mfma)
     return ranphy::status_of(
-        ranphy::launch_mmse_mfma(g, rx2, false, h2, h_res, noise_var, x2, nv, nullptr, precision,
-                                 s));
+        ranphy::launch_mmse_mfma(g, rx2, false, h2, nullptr, h_res, noise_var, x2, nv, nullptr,
+                                 precision, s));
   // Small arrays with one DMRS occasion: one thread per subcarrier shares the Gram and its
   // factorisation over the data symbols, once the batch has a subcarrier for every lane of
   // the chip (256 CUs x 4 SIMDs x 64 lanes); smaller batches (a single slot) finish sooner
@@ -222,8 +224,8 @@ int ranphy_mmse_llr(const ranphy_slot_desc* d, const float* rx, const float* h, 
     return RANPHY_ERR_INVALID;
   if (!ranphy::mmse_mfma_eligible(g, rx, h, x, nv, llr)) return RANPHY_ERR_UNSUPPORTED;
   return ranphy::status_of(ranphy::launch_mmse_mfma(
-      g, reinterpret_cast<const float2*>(rx), false, reinterpret_cast<const float2*>(h), h_res,
-      noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
+      g, reinterpret_cast<const float2*>(rx), false, reinterpret_cast<const float2*>(h), nullptr,
+      h_res, noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
       static_cast<hipStream_t>(stream)));
 }
 
@@ -248,7 +250,7 @@ int ranphy_mmse_llr_bfp(const ranphy_slot_desc* d, const uint32_t* packed, const
   if (!ranphy::mmse_mfma_eligible(g, nullptr, h, x, nv, llr)) return RANPHY_ERR_UNSUPPORTED;
   return ranphy::status_of(ranphy::launch_mmse_mfma(
       g, reinterpret_cast<const float2*>(packed), true, reinterpret_cast<const float2*>(h),
-      h_res, noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
+      nullptr, h_res, noise_var, reinterpret_cast<float2*>(x), nv, llr, precision,
       static_cast<hipStream_t>(stream)));
 }
 
@@ -358,16 +360,28 @@ int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const flo
 
 // ---- the whole chain in one launch (up to 8 layers) ----------------------------------------
 
+// More than 8 layers: the matrix-core detector, estimating its pilot rows itself.
+static int receive_mfma(const Geom& g, const void* rx, bool bfp, const float* pilots,
+                        const float* noise_var, float* llr, void* stream) {
+  if (!ranphy::mmse_mfma_eligible(g, bfp ? nullptr : rx, nullptr, nullptr, nullptr, llr))
+    return RANPHY_ERR_UNSUPPORTED;
+  return ranphy::status_of(ranphy::launch_mmse_mfma(
+      g, reinterpret_cast<const float2*>(rx), bfp, nullptr,
+      reinterpret_cast<const float2*>(pilots), RANPHY_H_PILOT, noise_var, nullptr, nullptr, llr,
+      RANPHY_PREC_FP32, static_cast<hipStream_t>(stream)));
+}
+
 int ranphy_receive(const ranphy_slot_desc* d, const float* rx, const float* pilots,
                    const float* noise_var, float* llr, void* stream) {
   Geom g;
   const int rc = ranphy::make_geom(d, &g);
   if (rc) return rc;
-  if (g.n_layers > ranphy::kBatchMaxLayers) return RANPHY_ERR_UNSUPPORTED;
   if (g.n_slots == 0) return RANPHY_OK;
   if (!ranphy::aligned8(rx) || !ranphy::aligned8(pilots) || !ranphy::aligned8(llr) ||
       noise_var == nullptr || ((uintptr_t)noise_var & 3u))
     return RANPHY_ERR_INVALID;
+  if (g.n_layers > ranphy::kBatchMaxLayers)
+    return receive_mfma(g, rx, false, pilots, noise_var, llr, stream);
   const int nk = ranphy::receive_tile(g, 256);
   if (nk < 1) return RANPHY_ERR_UNSUPPORTED;
   return ranphy::status_of(ranphy::launch_receive(
@@ -380,12 +394,15 @@ int ranphy_receive_bfp(const ranphy_slot_desc* d, const uint32_t* packed, const 
   Geom g;
   const int rc = ranphy::make_geom(d, &g);
   if (rc) return rc;
-  if (g.n_layers > ranphy::kBatchMaxLayers || ranphy::bfp_block(g.n_rx) == 0)
-    return RANPHY_ERR_UNSUPPORTED;
+  if (ranphy::bfp_block(g.n_rx) == 0) return RANPHY_ERR_UNSUPPORTED;
   if (g.n_slots == 0) return RANPHY_OK;
   if (packed == nullptr || ((uintptr_t)packed & 3u) || !ranphy::aligned8(pilots) ||
       !ranphy::aligned8(llr) || noise_var == nullptr || ((uintptr_t)noise_var & 3u))
     return RANPHY_ERR_INVALID;
+  if (g.n_layers > ranphy::kBatchMaxLayers) {  // the detector's words are read 8 bytes at a time
+    if ((uintptr_t)packed & 7u) return RANPHY_ERR_INVALID;
+    return receive_mfma(g, packed, true, pilots, noise_var, llr, stream);
+  }
   const int nk = ranphy::receive_tile(g, 256);
   if (nk < 1) return RANPHY_ERR_UNSUPPORTED;
   return ranphy::status_of(ranphy::launch_receive(

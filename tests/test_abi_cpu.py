@@ -116,10 +116,16 @@ def test_null_descriptor(L):
     assert L.ranphy_receive(None, P(8), P(8), P(8), P(8), None) == -1
 
 
-def test_one_launch_chain_rejects_more_than_8_layers(L):
+def test_one_launch_chain_above_8_layers_needs_the_matrix_core_shapes(L):
     P = ctypes.c_void_p
+    d = _desc(n_layers=9, n_rx=12, dmrs_comb=8, dmrs_td=2)  # 12 antennas: no matrix-core form
+    assert L.ranphy_receive(ctypes.byref(d), P(16), P(16), P(16), P(16), None) == -2
+    d = _desc(n_layers=9, n_rx=16, dmrs_comb=8, dmrs_td=2, dmrs_sym0=(2, 10))  # two occasions
+    assert L.ranphy_receive(ctypes.byref(d), P(16), P(16), P(16), P(16), None) == -2
     d = _desc(n_layers=9, n_rx=16, dmrs_comb=8, dmrs_td=2)
-    assert L.ranphy_receive(ctypes.byref(d), P(8), P(8), P(8), P(8), None) == -2
+    assert L.ranphy_receive(ctypes.byref(d), P(8), P(16), P(16), P(16), None) == -2  # rx 8-aligned
+    assert L.ranphy_receive(ctypes.byref(d), P(16), P(16), P(16), P(0x1008), None) == -2
+    assert L.ranphy_receive(ctypes.byref(d), P(16), P(16), P(0x1002), P(16), None) == -1
 
 
 def test_null_and_misaligned_pointers_rejected(L):

@@ -220,3 +220,55 @@ def test_receive_full_size_sampled(cfg):
         one = shape.with_slots(1)
         ref = oracle_chain(one, b["rx"][s:s + 1], b["pilots"][s:s + 1], b["noise_var"][s:s + 1])
         check(one, lg[s:s + 1], ref)
+
+
+MFMA_RECEIVE = {
+    "64x16_3prb": SlotShape(n_prb=3, n_symb=14, n_rx=64, n_layers=16, qm=6, dmrs_comb=8,
+                            dmrs_td=2, dmrs_sym0=(2,), n_slots=2),
+    "48x12_5prb": SlotShape(n_prb=5, n_symb=14, n_rx=48, n_layers=12, qm=4, dmrs_comb=8,
+                            dmrs_td=2, dmrs_sym0=(3,), n_slots=1),
+    "16x9_short": SlotShape(n_prb=4, n_symb=9, n_rx=16, n_layers=9, qm=8, dmrs_comb=8, dmrs_td=2,
+                            dmrs_sym0=(0,), n_slots=2),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MFMA_RECEIVE))
+def test_one_launch_above_8_layers_equals_two_call_chain(name):
+    """More than 8 layers: ranphy_receive runs the matrix-core detector with the pilot-resolution
+    estimate formed inside it (same arithmetic as ranphy_chest_ls), so its LLRs equal
+    ranphy_chest_ls -> ranphy_mmse_llr bit for bit (odd PRB counts put pilots past the band
+    edge; 48 antennas leave part of the staging threads idle); from BFP words likewise."""
+    shape = MFMA_RECEIVE[name]
+    say(f"receive > 8 layers {name}")
+    ds = [synth.make_slot(shape.with_slots(1), np.random.default_rng(600 + i), 30e3,
+                          ("exp", 1e-7), 20.0) for i in range(shape.n_slots)]
+    rx = dev(np.stack([d["rx"] for d in ds]))
+    pil = dev(np.stack([d["pilots"] for d in ds]))
+    nvar = torch.tensor([d["noise_var"] for d in ds], dtype=torch.float32, device="cuda")
+    h = ranphy.chest_ls(shape, rx, pil)
+    ref = ranphy.mmse_llr(shape, rx, h, nvar)
+    llr = ranphy.receive(shape, rx, pil, nvar)
+    words = ranphy.bfp_compress(shape, rx)
+    rxd = ranphy.bfp_decompress(shape, words)
+    ref_b = ranphy.mmse_llr(shape, rxd, ranphy.chest_ls(shape, rxd, pil), nvar)
+    llr_b = ranphy.receive_bfp(shape, words, pil, nvar)
+    torch.cuda.synchronize()
+    assert torch.equal(llr.view(torch.int32), ref.view(torch.int32))
+    assert torch.equal(llr_b.view(torch.int32), ref_b.view(torch.int32))
+    bits = np.stack([d["bits"] for d in ds]).reshape(-1)  # a sanity floor (256QAM at 20 dB)
+    assert np.mean((llr.cpu().numpy() < 0) == (bits > 0)) > 0.9
+
+
+def test_one_launch_64x16_full_size_equals_two_call_chain():
+    c = synth.CONFIGS["m"]
+    shape = c["shape"].with_slots(2)
+    say(f"receive full size {shape}")
+    ds = [synth.make_slot(shape.with_slots(1), synth.rng_for(c["config_id"], 3 + i, 0),
+                          c["scs_hz"], c["pdp"], c["snr_db"][3 + i]) for i in range(2)]
+    rx = dev(np.stack([d["rx"] for d in ds]))
+    pil = dev(np.stack([d["pilots"] for d in ds]))
+    nvar = torch.tensor([d["noise_var"] for d in ds], dtype=torch.float32, device="cuda")
+    ref = ranphy.mmse_llr(shape, rx, ranphy.chest_ls(shape, rx, pil), nvar)
+    llr = ranphy.receive(shape, rx, pil, nvar)
+    torch.cuda.synchronize()
+    assert torch.equal(llr.view(torch.int32), ref.view(torch.int32))
