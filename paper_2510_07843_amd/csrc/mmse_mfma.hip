@@ -600,12 +600,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     // gs whole groups of NR threads (NR <= 64); with 48 antennas the last 16 threads idle
     const int r = threadIdx.x % NR, gs = 256 / NR, g0 = threadIdx.x / NR;
     const int64_t sym_re = ((int64_t)slot * g.n_symb + g.sym0[0]) * g.n_sc;
+    // Only rows some subcarrier of the block interpolates from are formed: for comb offset c
+    // (shared by its ports), pilots j0 at k0 .. j1 at k0 + 3 (the rule is monotone in k); the
+    // rows left out are read by no wave of the block, the FP64 route included.
+    auto needed = [&](int gg) {
+      const int cc = gg & (C - 1), j = jlo + (gg >> g.comb_log2);
+      int ja, jb, jc, jd;
+      float a;
+      freq_rule(g, cc, k0, ja, jb, a);
+      freq_rule(g, cc, k0 + 3, jc, jd, a);
+      return j >= ja && j <= jd;
+    };
     float2 ys[kItems][2];
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int gg = g0 + it * gs;
       ys[it][0] = ys[it][1] = make_float2(0.f, 0.f);
-      if (g0 < gs && gg < nrow * C) {
+      if (g0 < gs && gg < nrow * C && needed(gg)) {
         const int kc = min(C * (jlo + (gg >> g.comb_log2)) + (gg & (C - 1)), g.n_sc - 1);
         ys[it][0] = rx_at<RXF>(rx, sym_re + kc, NR, r);
         if (T == 2) ys[it][1] = rx_at<RXF>(rx, sym_re + g.n_sc + kc, NR, r);
@@ -615,7 +626,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 #pragma unroll
     for (int it = 0; it < kItems; ++it) {
       const int gg = g0 + it * gs;
-      if (g0 < gs && gg < nrow * C) {
+      if (g0 < gs && gg < nrow * C && needed(gg)) {
         const int row = gg >> g.comb_log2, cc = gg & (C - 1);
         const bool in = C * (jlo + row) + cc < g.n_sc;
         for (int p = cc; p < NL; p += C) {
