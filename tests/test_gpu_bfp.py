@@ -363,3 +363,50 @@ def test_launch_chunking_past_2_26_blocks():
     assert np.array_equal(words.view(n_blocks, 10)[lo:hi].cpu().numpy().view(np.uint32).reshape(-1), wr)
     assert np.array_equal(bits(back.view(n_blocks, 16)[lo:hi].cpu().numpy().reshape(-1)),
                           bits(bref.decompress(wr, 16, sub.size)))
+
+
+def _replay_check(step, outs, refs):
+    """Capture `step` (writing `outs`) in a HIP graph after one eager warm-up on a side stream,
+    then replay it three times with eager work (refilling the outputs) between replays;
+    every replay must reproduce the eager results bit for bit."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for i in range(3):
+        for o in outs:
+            o.view(torch.int32).fill_(i - 7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, refs):
+            assert torch.equal(o.view(torch.int32), r.view(torch.int32)), i
+
+
+def test_graph_replay_of_the_word_reading_chains():
+    """HIP-graph capture of the chains that read BFP words: the estimator and the
+    matrix-core detector (64 x 16), and the one-launch chain (16 x 4, two occasions)."""
+    shape = MFMA_SHAPES["64x16"]
+    words, pil, nvar = _batch(shape, 700)
+    h_ref = ranphy.chest_ls_bfp(shape, words, pil)
+    l_ref = ranphy.mmse_llr_bfp(shape, words, h_ref, nvar)
+    torch.cuda.synchronize()
+    h = torch.empty_like(h_ref)
+    llr = torch.empty_like(l_ref)
+
+    def step():
+        ranphy.chest_ls_bfp(shape, words, pil, h=h)
+        ranphy.mmse_llr_bfp(shape, words, h, nvar, llr=llr)
+    _replay_check(step, [h, llr], [h_ref, l_ref])
+
+    shape2 = RECEIVE_SHAPES["16x4_2occ_256qam"]
+    words2, pil2, nvar2 = _batch(shape2, 710)
+    ref2 = ranphy.receive_bfp(shape2, words2, pil2, nvar2)
+    torch.cuda.synchronize()
+    out2 = torch.empty_like(ref2)
+    _replay_check(lambda: ranphy.receive_bfp(shape2, words2, pil2, nvar2, llr=out2), [out2], [ref2])

@@ -272,3 +272,29 @@ def test_one_launch_64x16_full_size_equals_two_call_chain():
     llr = ranphy.receive(shape, rx, pil, nvar)
     torch.cuda.synchronize()
     assert torch.equal(llr.view(torch.int32), ref.view(torch.int32))
+
+
+def test_one_launch_above_8_layers_graph_replay():
+    shape = MFMA_RECEIVE["48x12_5prb"]
+    ds = [synth.make_slot(shape.with_slots(1), np.random.default_rng(650), 30e3, ("exp", 1e-7),
+                          15.0)]
+    rx, pil = dev(np.stack([d["rx"] for d in ds])), dev(np.stack([d["pilots"] for d in ds]))
+    nvar = torch.tensor([d["noise_var"] for d in ds], dtype=torch.float32, device="cuda")
+    ref = ranphy.receive(shape, rx, pil, nvar)
+    torch.cuda.synchronize()
+    out = torch.empty_like(ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ranphy.receive(shape, rx, pil, nvar, llr=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ranphy.receive(shape, rx, pil, nvar, llr=out)
+    for i in range(3):
+        out.fill_(float(i) - 9.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out.view(torch.int32), ref.view(torch.int32)), i
