@@ -763,6 +763,10 @@ def main():
                 variants[key] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
                                  "kernels_ms": v_k}
                 variants[key].update(quality[name])
+        if path != "receive":  # the whole chain as one launch (pilot rows estimated per block)
+            v_ms, v_k = run_timed(ranphy.PREC_FP32, True, one_launch=True)
+            variants["fp32_one_launch"] = {"value": re / (v_ms * 1e-3), "ms_per_step": v_ms,
+                                           "kernels_ms": v_k}
         if not args.no_learned:
             params, min_nv, report = train_refinement(torch, ranphy, synth, shape)
             nimg = shape.n_rx * shape.n_layers
