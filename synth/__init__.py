@@ -339,6 +339,16 @@ def make_batch(name: str, n_slots: Optional[int] = None, snr_db: Optional[Sequen
     return out
 
 
+def batch_slot(name: str, i: int) -> dict:
+    """Slot i of ``make_batch(name)`` (default SNR grid, first_slot 0) drawn on its own: the
+    same seeded stream, so the same bytes as that slot of the whole batch."""
+    cfg = CONFIGS[name]
+    grid = cfg["snr_db"]
+    si, sl = i % len(grid), i // len(grid)
+    rng = rng_for(cfg["config_id"], si, sl)
+    return make_slot(cfg["shape"].with_slots(1), rng, cfg["scs_hz"], cfg["pdp"], grid[si])
+
+
 # ---------------------------------------------------------------------------------------
 # DMRS-only slots with a time-varying channel (training and test data of the learned
 # refinement of the pilot-resolution estimate).

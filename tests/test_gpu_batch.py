@@ -1,7 +1,9 @@
 """GPU parity of the multi-UE persistent launch (ranphy_batch_*): every UE's LLRs against the
 FP64 oracle chain on that UE's slot, to the end-to-end bar of the single-UE tests (hard
-decisions bit-exact and LLRs within 1e-3 |LLR| + 1e-4 away from decision boundaries); graph
-replay; independence of the result from the tile size and the grid."""
+decisions bit-exact away from decision boundaries, every LLR within 1e-3 |LLR| + 1e-4 of the
+oracle's or inside the range the FP32 forward-error bound of its Gram allows, tests/parity.py);
+allocations up to the full 273 PRB; graph replay; independence of the result from the tile
+size and the grid."""
 import sys
 
 import numpy as np
@@ -12,6 +14,8 @@ import oracle
 import paper_2510_07843_amd as ranphy
 import synth
 from synth import SlotShape
+import parity
+from parity import say
 from paper_2510_07843_amd import tune
 
 pytestmark = pytest.mark.gpu
@@ -24,25 +28,7 @@ def gpu_ready():
     ranphy.lib()
 
 
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def axis_margin(x, qm):
-    m = qm // 2
-    scale = synth.qam_scale(qm)
-    out = np.zeros(x.shape + (qm,))
-    for ax, v in ((0, x.real), (1, x.imag)):
-        t = v * scale
-        for i in range(m):
-            if i > 0:
-                t = 2.0 ** (m - i) - np.abs(t)
-            out[..., 2 * i + ax] = np.abs(t) / scale
-    return out
-
-
-def make_ues(n, seed, max_prb=48):
+def make_ues(n, seed, max_prb=273):
     """UEs of random allocations: 4..max_prb PRB, 1..8 layers, 4..64 antennas, QPSK..256QAM,
     SNR 0..30 dB; one DMRS occasion (comb and cover by the layer count) or, for up to two
     layers, two single-symbol occasions (a time-varying channel estimate)."""
@@ -67,31 +53,32 @@ def make_ues(n, seed, max_prb=48):
     return ues
 
 
-def oracle_llr(u):
+def oracle_ref(u):
     sh = u["shape"]
-    hr = oracle.chest_ls(sh, u["rx_h"], u["pil_h"])
-    xr, nvr = oracle.mmse_detect(sh, u["rx_h"], hr.astype(np.complex64), oracle.H_PILOT, u["nv_h"])
-    return xr, oracle.llr_demap(sh, xr.astype(np.complex64), nvr.astype(np.float32))
+    hr = oracle.chest_ls(sh, u["rx_h"], u["pil_h"]).astype(np.complex64)
+    xr, nvr = oracle.mmse_detect(sh, u["rx_h"], hr, oracle.H_PILOT, u["nv_h"])
+    lr = oracle.llr_demap(sh, xr.astype(np.complex64), nvr.astype(np.float32))
+    return hr, xr, nvr, lr
 
 
 def test_batch_matches_oracle_per_ue():
+    # 24 UEs of 4..273 PRB (the workload's allocation range), 1..8 layers, 4..64 antennas.
     ues = make_ues(24, seed=1)
     b = ranphy.Batch(ues, tile_re=512)
-    say(f"batch of {len(ues)} UEs, {b.n_items} work items")
+    say(f"batch of {len(ues)} UEs ({sum(u['shape'].n_prb for u in ues)} PRB), "
+        f"{b.n_items} work items")
     b.run(256 * 2)
     torch.cuda.synchronize()
+    assert max(u["shape"].n_prb for u in ues) > 200
     for i, u in enumerate(ues):
         sh = u["shape"]
-        lg = u["llr"].cpu().numpy().reshape(sh.n_dsym, sh.n_sc, sh.n_layers, sh.qm)
-        xr, lr = oracle_llr(u)
-        lr = lr[0]
-        keep = (axis_margin(xr[0], sh.qm) > 1e-3) & (np.abs(lr) > 1e-3)
-        mism = ((lg < 0) != (lr < 0)) & keep
-        ok = (np.abs(lg - lr) <= 1e-3 * np.abs(lr) + 1e-4) | ~keep
-        say(f"UE {i}: {sh.n_prb} PRB {sh.n_rx}x{sh.n_layers} qm {sh.qm} occ {sh.dmrs_sym0}: "
-            f"hard mismatches {int(mism.sum())}, LLR out of bar {int((~ok).sum())} of {ok.size}")
-        assert not mism.any()
-        assert (~ok).mean() < 1e-3
+        lg = u["llr"].cpu().numpy().reshape(1, sh.n_dsym, sh.n_sc, sh.n_layers, sh.qm)
+        hr, xr, nvr, lr = oracle_ref(u)
+        grams = parity.gram_fn(sh, hr, oracle.H_PILOT, u["nv_h"])
+        parity.audit_llrs(lg, lr, xr, nvr,
+                          parity.kappa_radius(grams, xr.reshape(-1, sh.n_layers), sh.n_layers),
+                          sh.qm, f"UE {i}: {sh.n_prb} PRB {sh.n_rx}x{sh.n_layers} qm {sh.qm} "
+                                 f"occ {sh.dmrs_sym0}")
 
 
 def test_batch_graph_replay_and_grid_independence():

@@ -6,8 +6,13 @@ BF16-rounded weights and inputs):
   * forward: |out_gpu - out_ref| <= 3e-2 max|y_ref| per element and the rms error <= 1e-2
     rms(y_ref), y = out - x the network's part (each of the three hidden activations is
     rounded to BF16, relative 2^-9);
-  * gradients: per tensor ||g_gpu - g_ref|| <= 5e-2 ||g_ref|| (BF16 activations and BF16
-    output gradients), loss within 1e-2 relative; padded channels exactly zero.
+  * gradients: every element within its own error bound (grad_bounds below: the BF16
+    rounding of each activation and each back-propagated gradient, relative 2^-8, and FP32
+    accumulation carried through the network in absolute values, with the ReLU masks counted
+    as unknown wherever the forward error could flip them), loss within 1e-2 relative, and
+    per tensor ||g_gpu - g_ref|| <= 5e-2 ||g_ref||; padded channels exactly zero;
+  * Adam: one step element by element against the update written from its definition in
+    FP64 (hyperparameters the FP32 values nearest 0.9, 0.999 and 1e-8).
 """
 import sys
 
@@ -64,6 +69,89 @@ def unpack(v):
         p[f"W{l}"] = v[l * 9248:l * 9248 + 9216].reshape(9, 32, 32)[:, :ci, :co].astype(np.float64)
         p[f"b{l}"] = v[l * 9248 + 9216:(l + 1) * 9248][:co].astype(np.float64)
     return p
+
+
+UB = 2.0 ** -8   # BF16 unit roundoff (8 significant bits)
+U32 = 2.0 ** -24
+
+
+def _conv_abs(e, W, rows, cols):
+    """sum_t |shift_t(e)| @ |W[t]| (no bias): the forward 3x3 correlation in absolute values."""
+    return C.conv(np.abs(e), np.abs(W), np.zeros(W.shape[2]), rows, cols)
+
+
+def _convT_abs(e, W, rows, cols):
+    """sum_t |shift_-t(e)| @ |W[t]|^T: the input-gradient correlation in absolute values."""
+    out = np.zeros(e.shape[:2] + (W.shape[1],))
+    for t, (dy, dx) in enumerate(C.TAPS):
+        out += C.shift(np.abs(e), rows, cols, -dy, -dx) @ np.abs(W[t]).T
+    return out
+
+
+def grad_bounds(x, target, p, rows, cols, ex0=None):
+    """Per-element bounds on |g_gpu - g_ref| for every parameter tensor, for a GPU that rounds
+    every hidden activation and every back-propagated gradient to BF16 and accumulates in FP32
+    (input x and weights already BF16 on both sides).  Error bounds travel with the values:
+      forward   e(z_l) <= |W_l| * (e(a_{l-1}) + UB (|a_{l-1}| + e(a_{l-1}))) + g_K |W_l| * |a_{l-1}|
+                e(a_l) <= e(z_l)                                    (ReLU is 1-Lipschitz)
+      output    e(dz_L) <= 2 e(out) / N (+ FP32 rounding)
+      backward  e(da) <= |W|^T * (e(dz) + UB (|dz| + e(dz))) + g_K |W|^T * |dz|
+                e(dz_l) <= e(da) where z_l > e(z_l), |da| + e(da) where |z_l| <= e(z_l)
+                (the GPU's ReLU mask may differ there), 0 where z_l < -e(z_l)
+      weights   e(g_W[t]) <= sum shift_t(|a| + ea) (|dz| + ed) - sum shift_t(|a|) |dz|
+                             + g_n sum shift_t(|a|) |dz|,  ea, ed the rounded values' bounds
+    with g_K = K 2^-24 for sums of K terms; ex0 bounds an error of the input itself (0 when
+    both sides read the same BF16 input).  Returns {name: bound array}."""
+    n_out = x.size
+    acts = [x]
+    zs = []
+    errs = [np.zeros_like(x) if ex0 is None else ex0]
+    a = x
+    for l in range(C.N_LAYERS):
+        W, b = p[f"W{l}"], p[f"b{l}"]
+        ea_in = errs[-1] + UB * (np.abs(a) + errs[-1]) if l > 0 else errs[-1]
+        K = 9 * W.shape[1] + 1  # the products and the bias
+        z = C.conv(a, W, b, rows, cols)
+        ez = _conv_abs(ea_in, W, rows, cols) + K * U32 * (_conv_abs(a, W, rows, cols) + np.abs(b))
+        zs.append((z, ez))
+        if l < C.N_LAYERS - 1:
+            a = np.maximum(z, 0.0)
+            acts.append(a)
+            errs.append(ez)
+    y, ey = zs[-1]
+    out = x + y
+    eout = ey + U32 * np.abs(out)
+    dz = 2.0 * (out - target) / n_out
+    edz = 2.0 * eout / n_out + 2 * U32 * np.abs(dz)
+    bounds = {}
+    for l in range(C.N_LAYERS - 1, -1, -1):
+        a_in = acts[l]
+        ea_in = errs[l] + (UB * (np.abs(a_in) + errs[l]) if l > 0 else 0.0)
+        edz_r = edz + UB * (np.abs(dz) + edz)  # the BF16 gradient the kernels read
+        n_terms = a_in.shape[0] * a_in.shape[1]
+        eb = np.sum(edz_r, axis=(0, 1)) + n_terms * U32 * np.sum(np.abs(dz), axis=(0, 1))
+        eW = []
+        for (dy, dx) in C.TAPS:
+            sa = np.abs(C.shift(a_in, rows, cols, dy, dx))
+            se = C.shift(ea_in if np.ndim(ea_in) else np.zeros_like(a_in), rows, cols, dy, dx)
+            full = np.einsum("pbi,pbo->io", sa + se, np.abs(dz) + edz_r)
+            base = np.einsum("pbi,pbo->io", sa, np.abs(dz))
+            eW.append(full - base + n_terms * U32 * base)
+        bounds[f"W{l}"] = np.stack(eW)
+        bounds[f"b{l}"] = eb
+        if l == 0:
+            break
+        W = p[f"W{l}"]
+        da = np.zeros_like(a_in)
+        for t, (dy, dx) in enumerate(C.TAPS):
+            da += C.shift(dz, rows, cols, -dy, -dx) @ W[t].T
+        K = 9 * W.shape[2]
+        eda = _convT_abs(edz_r, W, rows, cols) + K * U32 * _convT_abs(dz, W, rows, cols)
+        z, ez = zs[l - 1]
+        unsure = np.abs(z) <= ez
+        dz = da * (z > 0)
+        edz = np.where(unsure, np.abs(da) + eda, np.where(z > 0, eda, 0.0))
+    return bounds
 
 
 def test_padded_entries_of_the_packing():
@@ -128,10 +216,15 @@ def test_gradients_match_oracle(rows, cols, nimg, ngrp):
     say(f"  loss gpu {loss.item():.6f} oracle {Lr:.6f}")
     assert abs(loss.item() - Lr) <= 1e-2 * Lr
     gg = unpack(gv)
+    eb = grad_bounds(xa, ta, p, rows, cols)
     for name in sorted(gr):
         rel = np.linalg.norm(gg[name] - gr[name]) / np.linalg.norm(gr[name])
-        say(f"  {name}: relative error {rel:.3e}")
+        err = np.abs(gg[name] - gr[name])
+        ratio = np.max(err / np.maximum(eb[name], 1e-300))
+        say(f"  {name}: relative error {rel:.3e}; largest error / element bound {ratio:.3f}, "
+            f"median bound / |g| {np.median(eb[name] / np.maximum(np.abs(gr[name]), 1e-30)):.1e}")
         assert rel <= 5e-2, name
+        assert np.all(err <= eb[name]), (name, np.argwhere(err > eb[name])[:5])
     # padded channels carry exactly zero gradient
     full = pack({k: v for k, v in gg.items()})
     assert np.array_equal(gv[:9216].reshape(9, 32, 32)[:, 2:, :], np.zeros((9, 30, 32)))
@@ -211,10 +304,57 @@ def test_noise_normalised_forward_and_gradients():
     say(f"  loss gpu {loss.item():.6f} oracle {Lr:.6f}")
     assert abs(loss.item() - Lr) <= 1e-2 * Lr
     gg = unpack(grad.cpu().numpy())
+    xb = bf16_round(xa).astype(np.float64)
+    # the GPU divides by sigma in FP32 before rounding to BF16: its input may sit one BF16 step
+    # from the oracle's (rounded from the FP64 quotient)
+    eb = grad_bounds(xb, ta, p, rows, cols, ex0=2 * UB * np.abs(xb))
     for name in sorted(gr):
         rel = np.linalg.norm(gg[name] - gr[name]) / np.linalg.norm(gr[name])
-        say(f"  {name}: relative error {rel:.3e}")
+        err = np.abs(gg[name] - gr[name])
+        say(f"  {name}: relative error {rel:.3e}; largest error / element bound "
+            f"{np.max(err / np.maximum(eb[name], 1e-300)):.3f}")
         assert rel <= 5e-2, name
+        assert np.all(err <= eb[name]), (name, np.argwhere(err > eb[name])[:5])
+
+
+@pytest.mark.parametrize("step", [1, 7, 1000])
+def test_adam_step_matches_its_definition(step):
+    # One step of cnn_adam against Adam written out in FP64 (Kingma and Ba):
+    #   m' = b1 m + (1 - b1) g,  v' = b2 v + (1 - b2) g^2,
+    #   p' = p - lr (m' / (1 - b1^t)) / (sqrt(v' / (1 - b2^t)) + eps),
+    # with b1, b2, eps the FP32 values nearest 0.9, 0.999, 1e-8 (the library's constants).
+    # Bound per element: a few FP32 roundings of each quantity, and the bias corrections
+    # 1 - b^t, formed in FP32 from a power with an ulp of error, whose relative error is up to
+    # ulp(b^t) / (1 - b^t).
+    rng = np.random.default_rng(step)
+    n = NP
+    p0 = rng.standard_normal(n).astype(np.float32)
+    g = (rng.standard_normal(n) * np.exp(rng.uniform(-6, 2, n))).astype(np.float32)
+    m0 = (rng.standard_normal(n) * 0.1).astype(np.float32) if step > 1 else np.zeros(n, np.float32)
+    v0 = (rng.uniform(0, 1, n) * 0.01).astype(np.float32) if step > 1 else np.zeros(n, np.float32)
+    lr = 2e-3
+    pd, gd, md, vd = (torch.from_numpy(a.copy()).cuda() for a in (p0, g, m0, v0))
+    ranphy.cnn_adam(pd, gd, md, vd, step, lr)
+    torch.cuda.synchronize()
+    pg, mg, vg = (t.cpu().numpy() for t in (pd, md, vd))
+    b1, b2, eps = (float(np.float32(c)) for c in (0.9, 0.999, 1e-8))
+    f = lambda a: a.astype(np.float64)
+    m1 = b1 * f(m0) + (1 - b1) * f(g)
+    v1 = b2 * f(v0) + (1 - b2) * f(g) ** 2
+    c1, c2 = 1 - b1 ** step, 1 - b2 ** step
+    upd = float(np.float32(lr)) * (m1 / c1) / (np.sqrt(v1 / c2) + eps)
+    p1 = f(p0) - upd
+    u = U32
+    assert np.all(np.abs(mg - m1) <= 4 * u * (b1 * np.abs(f(m0)) + (1 - b1) * np.abs(f(g)))
+                  + 1e-45)
+    assert np.all(np.abs(vg - v1) <= 4 * u * (b2 * f(v0) + (1 - b2) * f(g) ** 2) + 1e-45)
+    ulp = lambda b: np.spacing(np.float32(b))
+    rel = 16 * u + 2 * float(ulp(b1 ** step)) / c1 + float(ulp(b2 ** step)) / c2
+    err = np.abs(pg - p1)
+    bound = 2 * u * np.abs(p1) + rel * np.abs(upd)
+    say(f"adam step {step}: max |dp| {err.max():.2e}, largest error / bound "
+        f"{np.max(err / bound):.3f}")
+    assert np.all(err <= bound)
 
 
 def test_adam_learns_a_smoothing_map():

@@ -13,6 +13,8 @@ import oracle
 import paper_2510_07843_amd as ranphy
 import synth
 from synth import SlotShape
+import parity
+from parity import say
 
 pytestmark = pytest.mark.gpu
 
@@ -24,26 +26,8 @@ def gpu_ready():
     ranphy.lib()
 
 
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda().reshape(-1)
-
-
-def axis_margin(x, qm):
-    m = qm // 2
-    scale = synth.qam_scale(qm)
-    out = np.zeros(x.shape + (qm,))
-    for ax, v in ((0, x.real), (1, x.imag)):
-        t = v * scale
-        for i in range(m):
-            if i > 0:
-                t = 2.0 ** (m - i) - np.abs(t)
-            out[..., 2 * i + ax] = np.abs(t) / scale
-    return out
 
 
 def oracle_chain(shape, rx, pil, nvar):
@@ -53,57 +37,14 @@ def oracle_chain(shape, rx, pil, nvar):
     return dict(h=hr, x=xr, nv=nvr, llr=lr, noise_var=nvar)
 
 
-def kappa_interval(shape, ref, s, d, k, l, b):
-    """Range of the oracle's LLR for bit b of layer l at (slot s, data symbol d, subcarrier k)
-    over the FP32 forward-error ball of the detector: x moved by up to 8 kappa(G) Nl 2^-24 ||x||
-    per axis and the post-detection variance by the same relative amount.  Max-log LLRs are
-    piecewise linear in each axis value with kinks on the integer lattice of the normalised
-    constellation, so the range is attained at the ends of the interval or at a kink."""
-    H = oracle.channel_at(shape, ref["h"], oracle.H_PILOT, s, k, shape.data_symbols()[d])
-    G = oracle.gram(H, float(ref["noise_var"][s]))
-    delta = 8.0 * np.linalg.cond(G) * shape.n_layers * 2.0 ** -24
-    x0 = ref["x"][s, d, k, l]
-    r = delta * np.linalg.norm(ref["x"][s, d, k])
-    scale = synth.qam_scale(shape.qm)
-
-    def axis_points(v):
-        pts = [v - r, v, v + r]
-        lo, hi = np.ceil((v - r) * scale), np.floor((v + r) * scale)
-        pts += [z / scale for z in np.arange(lo, hi + 1)[:64]]
-        return np.asarray(pts)
-
-    re_, im_ = axis_points(x0.real), axis_points(x0.imag)
-    xs = (re_[:, None] + 1j * im_[None, :]).reshape(-1)
-    nv0 = ref["nv"][s, d, k, l]
-    xs = np.concatenate([xs, xs])
-    nvs = np.concatenate([np.full(xs.size // 2, nv0 * (1 - delta)),
-                          np.full(xs.size // 2, nv0 * (1 + delta))])
-    v = oracle.llr_batch(xs, nvs, shape.qm)[:, b]
-    return v.min(), v.max(), delta
-
-
-def check(shape, lg, ref):
+def check(shape, lg, ref, label="receive"):
     """Hard decisions bit-exact away from boundaries; every LLR within 1e-3 |LLR| + 1e-4 of
     the oracle's, or else inside the range the FP32 forward-error bound of its Gram matrix
-    allows (those are counted and printed)."""
-    xr, lr = ref["x"], ref["llr"]
-    keep = (axis_margin(xr, shape.qm) > 1e-3) & (np.abs(lr) > 1e-3)
-    mism = ((lg < 0) != (lr < 0)) & keep
-    tol = 1e-3 * np.abs(lr) + 1e-4
-    ok = (np.abs(lg - lr) <= tol) | ~keep
-    over = np.argwhere(~ok)
-    worst = 0.0
-    for (s, d, k, l, b) in over[:4000]:
-        lo, hi, delta = kappa_interval(shape, ref, int(s), int(d), int(k), int(l), int(b))
-        t = tol[s, d, k, l, b]
-        assert lo - t <= lg[s, d, k, l, b] <= hi + t, (s, d, k, l, b, lg[s, d, k, l, b],
-                                                        lr[s, d, k, l, b], lo, hi, delta)
-        worst = max(worst, delta)
-    say(f"  {lg.size} LLRs: hard mismatches {int(mism.sum())}, over 1e-3 {len(over)} (all in "
-        f"the kappa range, largest bound {worst:.1e}), excluded near boundaries "
-        f"{int((~keep).sum())}")
-    assert not mism.any()
-    assert len(over) <= 4000
+    allows (every such LLR audited; counts printed)."""
+    grams = parity.gram_fn(shape, ref["h"], oracle.H_PILOT, ref["noise_var"])
+    xr = ref["x"].reshape(-1, shape.n_layers)
+    parity.audit_llrs(lg, ref["llr"], ref["x"], ref["nv"],
+                      parity.kappa_radius(grams, xr, shape.n_layers), shape.qm, label)
 
 
 def make(shape, seed, snr_db=20.0, pdp=("exp", 100e-9), doppler=None):
