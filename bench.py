@@ -106,25 +106,64 @@ def fused_eligible(shape) -> bool:
             and shape.n_rx <= 64 and shape.n_dsym <= 16)
 
 
-def cpu_baseline(b, budget_s: float):
-    """The FP64 oracle on the host: whole slots of the same batch until the budget is used."""
+def host_cpu() -> dict:
+    """The host the oracle runs on: logical CPUs, the CPUs this process may use, the model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "model": model}
+
+
+def cpu_baseline(b, budget_s: float, reps: int = 5):
+    """The FP64 oracle on the host for a fixed sample of the batch (its first slot):
+    chest_ls + mmse_detect (LU route) + llr_demap, timed `reps` times on all the threads the
+    oracle uses and `reps` times on one thread, the median of each reported.  A leg stops
+    repeating once its runs have used `budget_s / 2` (at least one run each)."""
     import oracle
     shape = b["shape"]
-    n_done, t0 = 0, time.perf_counter()
+    one = shape.with_slots(1)
+    rx, pil, nvar = b["rx"][:1], b["pilots"][:1], b["noise_var"][:1]
     per_slot = shape.n_dsym * shape.n_sc
-    while n_done < shape.n_slots:
-        one = shape.with_slots(1)
-        rx = b["rx"][n_done:n_done + 1]
-        h = oracle.chest_ls(one, rx, b["pilots"][n_done:n_done + 1]).astype(np.complex64)
-        x, nv = oracle.mmse_detect(one, rx, h, oracle.H_PILOT, b["noise_var"][n_done:n_done + 1])
+
+    def once():
+        t0 = time.perf_counter()
+        h = oracle.chest_ls(one, rx, pil).astype(np.complex64)
+        x, nv = oracle.mmse_detect(one, rx, h, oracle.H_PILOT, nvar)
         oracle.llr_demap(one, x.astype(np.complex64), nv.astype(np.float32))
-        n_done += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=n_done * per_slot / dt, unit="RE/s", cores=oracle.threads(), kind="oracle",
-                sample=f"{n_done} of the {shape.n_slots} slots ({n_done * per_slot} data REs), "
-                       f"chest_ls + mmse_detect (LU route) + llr_demap in FP64, {dt:.1f} s")
+        return time.perf_counter() - t0
+
+    all_threads = oracle.threads()
+    legs = {}
+    try:
+        for n in (all_threads, 1):
+            oracle.set_threads(n)
+            ts, spent = [], 0.0
+            while len(ts) < reps and (not ts or spent < budget_s / 2):
+                ts.append(once())
+                spent += ts[-1]
+            legs[n] = {"value": per_slot / float(np.median(ts)), "runs": len(ts),
+                       "seconds": [round(t, 3) for t in ts]}
+    finally:
+        oracle.set_threads(all_threads)
+    cpu = host_cpu()
+    out = dict(value=legs[all_threads]["value"], unit="RE/s", cores=all_threads, kind="oracle",
+               sample=f"slot 0 of the batch ({per_slot} data REs), chest_ls + mmse_detect (LU "
+                      f"route) + llr_demap in FP64; median of {legs[all_threads]['runs']} runs "
+                      f"on {all_threads} threads",
+               runs_seconds=legs[all_threads]["seconds"], host=cpu)
+    out["single_thread"] = {"value": legs[1]["value"], "unit": "RE/s", "cores": 1,
+                            "runs_seconds": legs[1]["seconds"],
+                            "sample": f"the same slot, median of {legs[1]['runs']} runs"}
+    return out
 
 
 def detection_quality(torch, ranphy, synth):
@@ -530,7 +569,8 @@ def bench_batch(args, torch, ranphy, synth):
         dt = time.perf_counter() - t0
         out["cpu_baseline"] = dict(value=n / dt, unit="RE/s", cores=oracle.threads(), kind="oracle",
                                    sample=f"{done} of the {len(ues)} UEs ({n} data REs), chest_ls + "
-                                          f"mmse_detect (LU route) + llr_demap in FP64, {dt:.1f} s")
+                                          f"mmse_detect (LU route) + llr_demap in FP64, {dt:.1f} s",
+                                   host=host_cpu())
     print(json.dumps(out), flush=True)
 
 
@@ -552,7 +592,7 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "receive", "separate"],
                     help="fused detection + demapping (matrix-core shapes), the whole chain "
                          "in one launch (up to 8 layers) or three calls")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the one-slot latency runs (profiled runs: they launch the same "

@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
                                             ctypes.c_int, P, P, P]
         L.ranphy_ref_llr_batch.argtypes = [ctypes.c_int64, ctypes.c_int, P, P, P]
         L.ranphy_ref_qam_points.argtypes = [ctypes.c_int, P]
+        L.ranphy_ref_set_threads.argtypes = [ctypes.c_int]
+        L.ranphy_ref_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -168,6 +170,11 @@ def llr_batch(x: np.ndarray, nv, qm: int) -> np.ndarray:
 def threads() -> int:
     """OpenMP threads the oracle's loops use."""
     return int(lib().ranphy_ref_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's later loops on n threads (timing only; results do not change)."""
+    lib().ranphy_ref_set_threads(int(n))
 
 
 def qam_points(qm: int) -> np.ndarray:

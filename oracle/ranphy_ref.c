@@ -44,6 +44,16 @@ int ranphy_ref_threads(void) {
 #endif
 }
 
+/* Threads the following OpenMP loops of the calling thread use (n >= 1; no effect without
+ * OpenMP).  Timing only: the results do not depend on the thread count. */
+void ranphy_ref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------------------- */
 /* Descriptor helpers.                                                                    */
 /* ------------------------------------------------------------------------------------- */

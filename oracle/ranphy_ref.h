@@ -62,6 +62,7 @@ enum { RANPHY_REF_ROUTE_LU = 0, RANPHY_REF_ROUTE_RCOV = 1 };
 
 int ranphy_ref_version(void);
 int ranphy_ref_threads(void);
+void ranphy_ref_set_threads(int n); /* timing only: later OpenMP loops of this thread */
 
 /* Slot-level calls (host pointers). */
 int ranphy_ref_chest_ls(const ranphy_ref_desc* d, const float* rx, const float* pilots,
