@@ -54,7 +54,7 @@ __device__ __forceinline__ void freq_rule(const Geom& g, int p, int k, int& j0, 
   } else {
     j0 = (k - c) >> L;
     j1 = j0 + 1;
-    a = (float)(k - c - C * j0) * (1.f / (float)C);
+    a = ldexpf((float)(k - c - C * j0), -L);  // exact: / C with C = 2^L
   }
 }
 

@@ -215,6 +215,10 @@ __device__ __forceinline__ float2 bfp_sample(const unsigned* __restrict__ words,
                      ldexpf((float)((int)((unsigned)(f >> 9) << 23) >> 23), e));
 }
 
+// dst += (src0 of lane K of the lane's row of 16) * src1; K is asm operand 10.
+#define DPP_FMAC(dst, src0, src1) \
+  "v_fmac_f32_dpp " dst ", " src0 ", " src1 " row_newbcast:%10 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+
 // One Gauss-Jordan step on pivot K, with the pivot-column scaling deferred.  Lane (q, c)
 // holds R[4q+v][c] in (ar[v], ai[v]); the matrix of the textbook in-place elimination is
 // A[i][j] = R[i][j] s_j, where s_j = 1 until column j has been the pivot column and
@@ -223,7 +227,6 @@ __device__ __forceinline__ float2 bfp_sample(const unsigned* __restrict__ words,
 //   pivot column:  unchanged (its scale becomes s_K = -1/p)
 //   elsewhere:     R[i][j]  <- R[i][j] - R[i][K] R[K][j] / p
 // Every other update is linear in each column, so a uniform column scale commutes with it.
-// Each lane keeps s_c of its own column c in `scale`.
 // Each lane keeps s_c of its own column c in `scale`.  The pivots of the real layers are
 // also tracked: pmin / pmax hold the bit patterns of the smallest and largest (positive
 // floats order as their bit patterns; a pivot that is not positive fails `ok`).
@@ -250,18 +253,33 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& s
   const float rr = col_k ? 0.f : rw * pinv;
   const float ri = col_k ? 0.f : iw * pinv;
   scale = col_k ? -pinv : scale;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const float cr = row_bcast<K>(ar[v]);  // R[4q+v][K]
-    const float ci = row_bcast<K>(ai[v]);
-    float nr = fmaf(-cr, rr, fmaf(ci, ri, ar[v]));
-    float ni = fmaf(-cr, ri, fmaf(-ci, rr, ai[v]));
-    if (v == KV && q == KQ) {  // pivot row (4q + v == K only for v == K % 4)
-      nr = col_k ? -1.f : rr;
-      ni = ri;
-    }
-    ar[v] = nr;
-    ai[v] = ni;
+  // Rank-1 update of every element, with the broadcast of the pivot column folded into the
+  // multiply-adds (DPP row_newbcast on the first source of v_fmac_f32):
+  //   R[i][j] += bcast(ai) ri - bcast(ar) rr      (real part)
+  //   I[i][j] += -bcast(ai) rr - bcast(ar) ri     (imaginary part)
+  // with bcast(.) the value of lane K of the lane's row of 16, i.e. R[4q+v][K].  Lane K holds
+  // rr = ri = 0, so the broadcast sources never change during the update and each read sees
+  // the step's starting values; the two products of each part are added in the order
+  // fma(-cr, rr, fma(ci, ri, ar)) and fma(-cr, ri, fma(-ci, rr, ai)).  A VALU write followed
+  // by a DPP read of the same register needs two wait states: the block starts with them
+  // (values written just before it) and inside it every DPP source was written at least four
+  // instructions earlier.
+  asm volatile(
+      "s_nop 1\n\t"
+      DPP_FMAC("%0", "%4", "%8") DPP_FMAC("%1", "%5", "%8")
+      DPP_FMAC("%2", "%6", "%8") DPP_FMAC("%3", "%7", "%8")
+      DPP_FMAC("%4", "%4", "-%9") DPP_FMAC("%5", "%5", "-%9")
+      DPP_FMAC("%6", "%6", "-%9") DPP_FMAC("%7", "%7", "-%9")
+      DPP_FMAC("%0", "%0", "-%9") DPP_FMAC("%1", "%1", "-%9")
+      DPP_FMAC("%2", "%2", "-%9") DPP_FMAC("%3", "%3", "-%9")
+      DPP_FMAC("%4", "%0", "-%8") DPP_FMAC("%5", "%1", "-%8")
+      DPP_FMAC("%6", "%2", "-%8") DPP_FMAC("%7", "%3", "-%8")
+      : "+v"(ar[0]), "+v"(ar[1]), "+v"(ar[2]), "+v"(ar[3]), "+v"(ai[0]), "+v"(ai[1]),
+        "+v"(ai[2]), "+v"(ai[3])
+      : "v"(ri), "v"(rr), "n"(K));
+  if (q == KQ) {  // pivot row (4q + v == K only for v == K % 4)
+    ar[KV] = col_k ? -1.f : rr;
+    ai[KV] = ri;
   }
 }
 
@@ -712,15 +730,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     }
   }
 
-  // ---- 3. Gram on the matrix cores:  Re G = Hr^T Hr + Hi^T Hi,  P = Hr^T Hi --------------
+  // ---- 3. Gram on the matrix cores ---------------------------------------------------------
+  // FP32: two real products, P = Hr^T Hi and D = (Hr - Hi)^T (Hr - Hi) = Hr^T Hr + Hi^T Hi -
+  // P - P^T, so that Re G = D + (P + P^T) and Im G = P - P^T (P^T from the LDS transpose
+  // below).  16-bit inputs: acc_g = Hr^T Hr + Hi^T Hi and P directly (no difference of the
+  // rounded operands).
   floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, z_r = acc_g, z_i = acc_g;
   LowpH<half8> h16;
   LowpH<bf16x8> hb16;
   if constexpr (PREC == kPrecF32) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      acc_g = mfma(hr[s], hr[s], acc_g);
-      acc_g = mfma(hi[s], hi[s], acc_g);
+      const float hd = hr[s] - hi[s];
+      acc_g = mfma(hd, hd, acc_g);
       acc_p = mfma(hr[s], hi[s], acc_p);
     }
   } else if constexpr (PREC == kPrecF16) {
@@ -744,8 +766,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   for (int v = 0; v < 4; ++v) {
     const int i = 4 * q + v;
     const bool in = (i < NL) && (c < NL);
-    ar[v] = in ? acc_g[v] + ((i == c) ? s2 : 0.f) : ((i == c) ? 1.f : 0.f);
-    ai[v] = in ? acc_p[v] - tp[c * 17 + i] : 0.f;
+    const float pt = tp[c * 17 + i];  // P[c][i]
+    // P[i][c] + P[c][i] is the same sum for (i, c) and (c, i), so Re G stays symmetric
+    const float re = PREC == kPrecF32 ? acc_g[v] + (acc_p[v] + pt) : acc_g[v];
+    ar[v] = in ? re + ((i == c) ? s2 : 0.f) : ((i == c) ? 1.f : 0.f);
+    ai[v] = in ? acc_p[v] - pt : 0.f;
   }
   float gd[16];
   read_diag<0>(ar, gd);
@@ -785,7 +810,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
       }
       if constexpr (PREC == kPrecF32) {
         // Three real products (conj(a) b, a = hr + j hi, b = yr + j yi):
-        //   m1 = hr yr,  m2 = hi yi,  m3 = (hr - hi)(yr + yi);  Re = m1 + m2,  Im = m3 - m1 + m2.
+        //   m1 = hr yr,  m2 = hi yi,  m3 = (hr + hi)(yr - yi);  Re = m1 + m2,  Im = m1 - m2 - m3.
+        // (hr + hi rather than the Gram's hr - hi: nothing of the Gram's operands stays live
+        // across the inversion.)
         floatx4 acc_m1 = acc_g, acc_m2 = acc_g, acc_m3 = acc_g;
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc_m1[v] = acc_m2[v] = acc_m3[v] = 0.f;
@@ -793,12 +820,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
         for (int s = 0; s < 16; ++s) {
           acc_m1 = mfma(hr[s], yr[s], acc_m1);
           acc_m2 = mfma(hi[s], yi[s], acc_m2);
-          acc_m3 = mfma(hr[s] - hi[s], yr[s] + yi[s], acc_m3);
+          acc_m3 = mfma(hr[s] + hi[s], yr[s] - yi[s], acc_m3);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           z_r[v] = acc_m1[v] + acc_m2[v];
-          z_i[v] = acc_m3[v] - acc_m1[v] + acc_m2[v];
+          z_i[v] = acc_m1[v] - acc_m2[v] - acc_m3[v];
         }
       } else if constexpr (PREC == kPrecF16) {
         mf_lowp<half8, _Float16>(h16, yr, yi, z_r, z_i);
