@@ -243,6 +243,25 @@ RANPHY_API int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params
                                   const float* h_in, float* h_out, void* workspace,
                                   int64_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ranphy_cnn_denoise without a workspace argument.
+ * Its workspace is the library's own array of RANPHY_NOALLOC_SCRATCH_BYTES bytes in the
+ * device memory of each GPU it runs on, held until the process ends; the call allocates
+ * nothing (no hipMalloc, no allocating library routine).  The array belongs to the device of
+ * `stream` (the current device for the null stream); its device address is looked up once
+ * per device, on that device's first call.  Every call on one GPU shares the array, so calls
+ * whose executions overlap on one GPU (different streams, or graphs replayed concurrently)
+ * race and give undefined results; calls ordered on one stream do not.  Same arguments,
+ * semantics and results (bit for bit) as ranphy_cnn_denoise; slots are processed as many per
+ * pass as the array holds.  RANPHY_ERR_UNSUPPORTED when one slot needs more than the array
+ * (ranphy_cnn_workspace_bytes(n_occ, ceil(n_sc / C), n_rx * n_layers, 1, 0) >
+ * RANPHY_NOALLOC_SCRATCH_BYTES; e.g. one 64 x 16 slot of 273 PRB at comb 8 needs 1.7 MB, a
+ * two-occasion 64-image slot 12.9 MB), checked before anything runs on the GPU. */
+#define RANPHY_NOALLOC_SCRATCH_BYTES (32LL << 20)
+RANPHY_API int ranphy_cnn_denoise_noalloc(const ranphy_slot_desc* d, const float* params,
+                                          const float* noise_var, float min_noise_var,
+                                          const float* h_in, float* h_out, void* stream);
+
 /*
  * The whole chain in one launch for up to 8 layers: LS estimation at the pilots (abstract,
  * Sec. III-B), interpolation, LMMSE detection by Cholesky factorisation and substitution

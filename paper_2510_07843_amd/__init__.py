@@ -35,6 +35,7 @@ EXPORTED_SYMBOLS = (
     "ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec", "ranphy_mmse_llr",
     "ranphy_llr_demap", "ranphy_cnn_param_count", "ranphy_cnn_workspace_bytes",
     "ranphy_cnn_forward", "ranphy_cnn_grad", "ranphy_cnn_adam", "ranphy_cnn_denoise",
+    "ranphy_cnn_denoise_noalloc",
     "ranphy_batch_plan_bytes", "ranphy_batch_plan", "ranphy_batch_run", "ranphy_receive",
     "ranphy_bfp_words", "ranphy_bfp_compress", "ranphy_bfp_decompress", "ranphy_chest_ls_bfp",
     "ranphy_mmse_llr_bfp", "ranphy_receive_bfp",
@@ -109,6 +110,7 @@ def lib() -> ctypes.CDLL:
         L.ranphy_cnn_grad.argtypes = [P, P, P, P, P, P, I, I, I, I, P, I64, P]
         L.ranphy_cnn_adam.argtypes = [P, P, P, P, I, ctypes.c_float, P]
         L.ranphy_cnn_denoise.argtypes = [D, P, P, ctypes.c_float, P, P, P, I64, P]
+        L.ranphy_cnn_denoise_noalloc.argtypes = [D, P, P, ctypes.c_float, P, P, P]
         UE = ctypes.POINTER(UeRec)
         L.ranphy_batch_plan_bytes.argtypes = [UE, I, I]
         L.ranphy_batch_plan_bytes.restype = I64
@@ -124,7 +126,8 @@ def lib() -> ctypes.CDLL:
         L.ranphy_receive_bfp.argtypes = [D, P, P, P, P, P]
         for f in ("ranphy_chest_ls", "ranphy_mmse_detect", "ranphy_mmse_detect_prec",
                   "ranphy_mmse_llr", "ranphy_llr_demap", "ranphy_cnn_forward", "ranphy_cnn_grad",
-                  "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_batch_plan",
+                  "ranphy_cnn_adam", "ranphy_cnn_denoise", "ranphy_cnn_denoise_noalloc",
+                  "ranphy_batch_plan",
                   "ranphy_batch_run", "ranphy_receive", "ranphy_bfp_compress",
                   "ranphy_bfp_decompress", "ranphy_chest_ls_bfp", "ranphy_mmse_llr_bfp",
                   "ranphy_receive_bfp"):
@@ -458,6 +461,24 @@ def cnn_denoise(shape, params: torch.Tensor, h: torch.Tensor,
         ctypes.byref(d), _f32(params, "params", cnn_param_count()), pn, float(min_noise_var),
         _as_dev(h, "h", torch.complex64, nh), _as_dev(out, "out", torch.complex64, nh),
         workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return out
+
+
+def cnn_denoise_noalloc(shape, params: torch.Tensor, h: torch.Tensor,
+                        noise_var: Optional[torch.Tensor] = None, min_noise_var: float = 0.0,
+                        out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """cnn_denoise on the library's own device workspace: the call allocates nothing (``out``
+    must be given).  Calls that overlap on one GPU share that workspace and race."""
+    d = desc_of(shape)
+    nh = buffer_floats(d, BUF_H, H_PILOT)
+    if out is None:
+        raise ValueError("out is required: this call allocates nothing")
+    pn = None if noise_var is None else _as_dev(noise_var, "noise_var", torch.float32,
+                                                buffer_floats(d, BUF_NOISE_VAR))
+    _check("ranphy_cnn_denoise_noalloc", lib().ranphy_cnn_denoise_noalloc(
+        ctypes.byref(d), _f32(params, "params", cnn_param_count()), pn, float(min_noise_var),
+        _as_dev(h, "h", torch.complex64, nh), _as_dev(out, "out", torch.complex64, nh),
+        _stream(stream)))
     return out
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "batch.h"
@@ -325,19 +326,15 @@ int ranphy_cnn_adam(float* params, const float* grad, float* m, float* v, int st
       ranphy::cnn_adam(params, grad, m, v, step, lr, static_cast<hipStream_t>(stream)));
 }
 
-int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const float* noise_var,
-                       float min_noise_var, const float* h_in, float* h_out, void* workspace,
-                       int64_t workspace_bytes, void* stream) {
-  Geom g;
-  const int rc = ranphy::make_geom(d, &g);
-  if (rc) return rc;
-  if (g.n_slots == 0) return RANPHY_OK;
+}  // extern "C"
+
+// The refinement of a pilot-resolution estimate over a caller's or the library's workspace:
+// as many slots per pass as `workspace_bytes` holds (one slot at least, else
+// RANPHY_ERR_UNSUPPORTED).  Arguments are validated by the callers.
+static int denoise_passes(const Geom& g, const float* params, const float* noise_var,
+                          float min_noise_var, const float* h_in, float* h_out, void* workspace,
+                          int64_t workspace_bytes, hipStream_t s) {
   const int rows = g.n_occ, cols = g.n_pilot, nimg = g.n_rx * g.n_layers;
-  if (workspace == nullptr || ((uintptr_t)workspace & 255u) || !aligned4(params) ||
-      !ranphy::aligned8(h_in) || !ranphy::aligned8(h_out) ||
-      (noise_var != nullptr && !aligned4(noise_var)) || !(min_noise_var >= 0.f))
-    return RANPHY_ERR_INVALID;
-  // as many slots per pass as the workspace holds
   int chunk = 0;
   for (int c = g.n_slots; c >= 1; c = c / 2) {
     if (ranphy::cnn_workspace_bytes(rows, cols, nimg, c, false) <= workspace_bytes) {
@@ -345,9 +342,8 @@ int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const flo
       break;
     }
   }
-  if (chunk == 0) return RANPHY_ERR_INVALID;
+  if (chunk == 0) return RANPHY_ERR_UNSUPPORTED;
   const int64_t per_slot = (int64_t)rows * cols * nimg * 2;  // floats
-  hipStream_t s = static_cast<hipStream_t>(stream);
   for (int s0 = 0; s0 < g.n_slots; s0 += chunk) {
     const int n = g.n_slots - s0 < chunk ? g.n_slots - s0 : chunk;
     const hipError_t e = ranphy::cnn_forward(
@@ -356,6 +352,86 @@ int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const flo
     if (e != hipSuccess) return RANPHY_ERR_LAUNCH;
   }
   return RANPHY_OK;
+}
+
+static int denoise_check(const Geom& g, const float* params, const float* noise_var,
+                         float min_noise_var, const float* h_in, const float* h_out) {
+  if (!aligned4(params) || !ranphy::aligned8(h_in) || !ranphy::aligned8(h_out) ||
+      (noise_var != nullptr && !aligned4(noise_var)) || !(min_noise_var >= 0.f))
+    return RANPHY_ERR_INVALID;
+  return RANPHY_OK;
+}
+
+// ---- the library's own workspace for ranphy_cnn_denoise_noalloc --------------------------
+// One array per GPU, in device memory for the life of the process.  Host code never uses the
+// array's name as an address (on the host it names a stand-in): the device address comes
+// from hipGetSymbolAddress, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[RANPHY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices];  // device address of `scratch` per device, once looked up
+
+// Device address of `scratch` on the device of stream s (the current device for the null
+// stream).  0 on success, else a RANPHY error.
+int scratch_for(hipStream_t s, void** out) {
+  int cur = -1, dev = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return RANPHY_ERR_LAUNCH;
+  dev = cur;
+  if (s != nullptr && hipStreamGetDevice(s, &dev) != hipSuccess) return RANPHY_ERR_INVALID;
+  if (dev < 0 || dev >= kMaxDevices) return RANPHY_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_dev[dev] == nullptr) {
+    if (dev != cur && hipSetDevice(dev) != hipSuccess) return RANPHY_ERR_LAUNCH;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) (void)hipSetDevice(cur);
+    if (e != hipSuccess || p == nullptr) return RANPHY_ERR_LAUNCH;
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return RANPHY_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ranphy_cnn_denoise(const ranphy_slot_desc* d, const float* params, const float* noise_var,
+                       float min_noise_var, const float* h_in, float* h_out, void* workspace,
+                       int64_t workspace_bytes, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (g.n_slots == 0) return RANPHY_OK;
+  if (workspace == nullptr || ((uintptr_t)workspace & 255u)) return RANPHY_ERR_INVALID;
+  const int rc2 = denoise_check(g, params, noise_var, min_noise_var, h_in, h_out);
+  if (rc2) return rc2;
+  const int rc3 = denoise_passes(g, params, noise_var, min_noise_var, h_in, h_out, workspace,
+                                 workspace_bytes, static_cast<hipStream_t>(stream));
+  // a workspace too small for one slot is the caller's argument error here
+  return rc3 == RANPHY_ERR_UNSUPPORTED ? RANPHY_ERR_INVALID : rc3;
+}
+
+int ranphy_cnn_denoise_noalloc(const ranphy_slot_desc* d, const float* params,
+                               const float* noise_var, float min_noise_var, const float* h_in,
+                               float* h_out, void* stream) {
+  Geom g;
+  const int rc = ranphy::make_geom(d, &g);
+  if (rc) return rc;
+  if (g.n_slots == 0) return RANPHY_OK;
+  const int rc2 = denoise_check(g, params, noise_var, min_noise_var, h_in, h_out);
+  if (rc2) return rc2;
+  // one slot must fit the array; checked before anything touches the GPU
+  if (ranphy::cnn_workspace_bytes(g.n_occ, g.n_pilot, g.n_rx * g.n_layers, 1, false) >
+      RANPHY_NOALLOC_SCRATCH_BYTES)
+    return RANPHY_ERR_UNSUPPORTED;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* ws = nullptr;
+  const int rc3 = scratch_for(s, &ws);
+  if (rc3) return rc3;
+  return denoise_passes(g, params, noise_var, min_noise_var, h_in, h_out, ws,
+                        RANPHY_NOALLOC_SCRATCH_BYTES, s);
 }
 
 // ---- the whole chain in one launch (up to 8 layers) ----------------------------------------

@@ -312,3 +312,31 @@ def test_fused_bfp_validation(L):
                                 None) == -2
     assert L.ranphy_receive_bfp(ctypes.byref(m), P(8), P(8), P(8), P(8), None) == -2  # 16 layers
     assert L.ranphy_receive_bfp(ctypes.byref(_desc(n_slots=0)), P(0), P(0), P(0), P(0), None) == 0
+
+
+def test_cnn_denoise_noalloc_validation(L):
+    # The no-allocation refinement validates everything, and rejects slots whose workspace
+    # exceeds the library's own array, before it looks up that array or touches the GPU.
+    P = ctypes.c_void_p
+    f = L.ranphy_cnn_denoise_noalloc
+    f.argtypes = [ctypes.POINTER(ranphy.SlotDesc), P, P, ctypes.c_float, P, P, P]
+    f.restype = ctypes.c_int
+    L.ranphy_cnn_workspace_bytes.restype = ctypes.c_int64
+    limit = 32 << 20  # RANPHY_NOALLOC_SCRATCH_BYTES
+    # 64 x 16 at 273 PRB, comb 8 x 2 symbols: one slot is a one-row grid of 410 x 1024 images
+    m = _desc(n_prb=273, n_rx=64, n_layers=16, qm=6, dmrs_comb=8, dmrs_td=2, dmrs_sym0=(2,),
+              n_slots=140)
+    assert L.ranphy_cnn_workspace_bytes(1, 410, 1024, 1, 0) <= limit
+    # the same with two occasions keeps every layer's activations: far beyond the array
+    big = _desc(n_prb=273, n_rx=64, n_layers=16, qm=6, dmrs_comb=8, dmrs_td=2,
+                dmrs_sym0=(2, 9), n_slots=1)
+    assert L.ranphy_cnn_workspace_bytes(2, 410, 1024, 1, 0) > limit
+    assert f(ctypes.byref(big), P(0x1000), None, 0.0, P(0x1000), P(0x1000), None) == -2
+    assert f(ctypes.byref(m), None, None, 0.0, P(0x1000), P(0x1000), None) == -1
+    assert f(ctypes.byref(m), P(0x1000), None, 0.0, P(0x1004), P(0x1000), None) == -1
+    assert f(ctypes.byref(m), P(0x1000), P(0x1002), 0.0, P(0x1000), P(0x1000), None) == -1
+    assert f(ctypes.byref(m), P(0x1000), None, -1.0, P(0x1000), P(0x1000), None) == -1
+    assert f(None, P(0x1000), None, 0.0, P(0x1000), P(0x1000), None) == -1
+    empty = _desc(n_prb=273, n_rx=64, n_layers=16, qm=6, dmrs_comb=8, dmrs_td=2,
+                  dmrs_sym0=(2,), n_slots=0)
+    assert f(ctypes.byref(empty), P(0x1000), None, 0.0, P(0x1000), P(0x1000), None) == 0
