@@ -68,6 +68,23 @@ def measured_traffic(kernel: str, tag: str):
     return float(fields[f"{kernel}_traffic_bytes_per_launch"])
 
 
+def measured_counters(kernel: str, prec: str, tag: str):
+    """Per-wave instruction counts and busy fractions of ``kernel`` from the committed
+    rocprofv3 SQ-counter summary for this workload and precision (VALU instructions other
+    than MFMA per wave, MFMA per wave, the fractions of the SIMD cycles the MFMA and the
+    other VALU instructions occupy), or None when there is none or the kernel's source has
+    changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"counters_{kernel}_{prec}_{tag}.md")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    key = f"{kernel}_{prec}_"
+    fields = dict(l.split(": ", 1) for l in open(path).read().splitlines() if l.startswith(key))
+    if fields.get(key + "source_sha256") != source_digest(kernel):
+        return None
+    return {n: float(fields[key + n]) for n in ("valu_per_wave", "mfma_per_wave",
+                                                 "mfma_busy_frac", "valu_busy_frac")}
+
+
 def algorithmic_costs(shape, h_res=0):
     """Per-launch algorithmic HBM bytes and flops of each call (each input read once, each
     output written once; flops of the method's own arithmetic in the z-form: Hermitian half
@@ -531,7 +548,8 @@ def bench_batch(args, torch, ranphy, synth):
                     unit="TFLOP/s")
     roof.update(frac=roof["achieved"] / roof["peak"], kernel="batch_kernel",
                 traffic=measured_traffic("batch_kernel", f"batch_{len(ues)}ues"),
-                algorithmic_bytes=nbytes, algorithmic_flops=flops)
+                algorithmic_bytes=nbytes, algorithmic_flops=flops,
+                counters=measured_counters("batch_kernel", "fp32", f"batch_{len(ues)}ues"))
     shapes = [u["shape"] for u in ues]
     out = {
         "metric": "REs/s detected, 64Rx×16L MMSE: FP32 plain vs mixed/learned at ≤0.1 dB loss",
@@ -741,6 +759,10 @@ def main():
                        else None)
     roof["algorithmic_bytes"] = c["bytes"]
     roof["algorithmic_flops"] = c["flops"]
+    # SQ counters of the same kernel (committed summary): per-wave VALU / MFMA instructions
+    # and the shares of the SIMD cycles they occupy (FP32 MFMA and VALU issue do not overlap)
+    roof["counters"] = (measured_counters(dom, args.prec, tag) if h_res == ranphy.H_PILOT
+                        else None)
 
     out = {
         "metric": "REs/s detected, 64Rx×16L MMSE: FP32 plain vs mixed/learned at ≤0.1 dB loss",

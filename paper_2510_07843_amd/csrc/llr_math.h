@@ -19,18 +19,31 @@ namespace ranphy {
 
 // The sign of each LLR is the sign of t_i.  Where t_i is zero (u on that bit's boundary) the
 // numerator is zero too, so the sign of zero never matters.
+//
+// axis_llr takes uh = u / 2 (the axis value times scale / 2, which is exactly half of the
+// value times scale): floor(u / 2) needs no extra multiply, and every use of u is formed
+// from uh with an exact doubling inside a fused multiply-add, so each rounded result is the
+// one the same expression in u would give.
 template <int M>
-__device__ __forceinline__ void axis_llr(float u, float inv, float* out /* stride 2 */) {
+__device__ __forceinline__ void axis_llr(float uh, float inv, float* out /* stride 2 */) {
   constexpr float lim = (float)((1 << M) - 1);
-  float a = 2.f * floorf(0.5f * u) + 1.f;
+  float a = fmaf(floorf(uh), 2.f, 1.f);
   a = fminf(fmaxf(a, -lim), lim);
-  const float e = u - a;
+  const float e = fmaf(uh, 2.f, -a);  // u - a
   const float e2 = e * e;
-  float t = u;
+  float t = uh;                       // t_0 = u: only its sign and |u| + 1 are used
 #pragma unroll
   for (int i = 0; i < M; ++i) {
-    if (i > 0) t = (float)(1 << (M - i)) - fabsf(t);
-    const float dd = fabsf(t) + 1.f;
+    float dd;
+    if (i == 0) {
+      dd = fmaf(fabsf(uh), 2.f, 1.f);  // |u| + 1
+    } else if (i == 1) {
+      t = fmaf(-fabsf(uh), 2.f, (float)(1 << (M - 1)));  // 2^(m-1) - |u|
+      dd = fabsf(t) + 1.f;
+    } else {
+      t = (float)(1 << (M - i)) - fabsf(t);
+      dd = fabsf(t) + 1.f;
+    }
     out[2 * i] = copysignf(fmaf(dd, dd, -e2) * inv, t);
   }
 }
@@ -42,10 +55,10 @@ template <int QM>
 __device__ __forceinline__ void llr_one(float2 v, float nvv, float* out) {
   constexpr int M = QM / 2;
   constexpr float sc2 = 2.f * (float)((1 << QM) - 1) / 3.f;  // scale^2
-  const float scale = __builtin_sqrtf(sc2);
+  const float half_scale = 0.5f * __builtin_sqrtf(sc2);          // exact halving
   const float inv = __builtin_amdgcn_rcpf(sc2 * nvv);
-  axis_llr<M>(v.x * scale, inv, out);
-  axis_llr<M>(v.y * scale, inv, out + 1);
+  axis_llr<M>(v.x * half_scale, inv, out);
+  axis_llr<M>(v.y * half_scale, inv, out + 1);
 }
 
 }  // namespace ranphy

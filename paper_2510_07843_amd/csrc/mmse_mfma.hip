@@ -228,21 +228,29 @@ __device__ __forceinline__ float2 bfp_sample(const unsigned* __restrict__ words,
 //   elsewhere:     R[i][j]  <- R[i][j] - R[i][K] R[K][j] / p
 // Every other update is linear in each column, so a uniform column scale commutes with it.
 // Each lane keeps s_c of its own column c in `scale`.  The pivots of the real layers are
-// also tracked: pmin / pmax hold the bit patterns of the smallest and largest (positive
-// floats order as their bit patterns; a pivot that is not positive fails `ok`).
+// also tracked: pmin / pmax hold the bit patterns of the smallest and largest.
+//
+// The pivot tests run on the scalar unit, on bit patterns: the pivot p must exceed its
+// threshold th (16 FLT_EPSILON times the original diagonal entry, rounded as an FP32
+// product; th >= 0) and be finite.  For th >= 0 and p not NaN, p > th exactly when the
+// patterns read as signed integers compare so (positive floats order as their patterns,
+// negative ones read as negative integers); NaN and +inf have patterns at or above
+// 0x7f800000 and fail (an infinite pivot only comes from an overflowed Gram).
 template <int K>
 __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& scale, int q,
-                                        int c, int nl, const float (&gd)[16], bool& ok,
+                                        int c, int nl, const int (&thb)[16], bool& ok,
                                         unsigned& pmin, unsigned& pmax) {
   constexpr int KV = K & 3;
   constexpr int KQ = K >> 2;
-  const float p = uniform_read(ar[KV], 16 * KQ + K);
+  const unsigned pb = (unsigned)__builtin_amdgcn_readlane(__float_as_int(ar[KV]), 16 * KQ + K);
+  const float p = __uint_as_float(pb);
   // A pivot that is not positive relative to its original diagonal entry means the matrix
   // is not numerically positive definite; padded layers carry an identity block.
-  ok = ok && (K >= nl || p > PivotRel<float>::v * gd[K]);
   if (K < nl) {
-    pmin = min(pmin, __float_as_uint(p));
-    pmax = max(pmax, __float_as_uint(p));
+    ok = ok && (int)pb > thb[K] && pb < 0x7f800000u;
+    // scalar min / max (the compiler would fold pairs of them into vector min3 / max3)
+    asm("s_min_u32 %0, %1, %2" : "=s"(pmin) : "s"(pmin), "s"(pb) : "scc");
+    asm("s_max_u32 %0, %1, %2" : "=s"(pmax) : "s"(pmax), "s"(pb) : "scc");
   }
   const float pinv = __builtin_amdgcn_rcpf(p);
   // Row K at this lane's column c (row group K/4, register K%4), scaled; zero in the pivot
@@ -285,19 +293,21 @@ __device__ __forceinline__ void gj_step(float (&ar)[4], float (&ai)[4], float& s
 
 template <int K>
 __device__ __forceinline__ void gj_all(float (&ar)[4], float (&ai)[4], float& scale, int q,
-                                       int c, int nl, const float (&gd)[16], bool& ok,
+                                       int c, int nl, const int (&thb)[16], bool& ok,
                                        unsigned& pmin, unsigned& pmax) {
   if constexpr (K < 16) {
-    gj_step<K>(ar, ai, scale, q, c, nl, gd, ok, pmin, pmax);
-    gj_all<K + 1>(ar, ai, scale, q, c, nl, gd, ok, pmin, pmax);
+    gj_step<K>(ar, ai, scale, q, c, nl, thb, ok, pmin, pmax);
+    gj_all<K + 1>(ar, ai, scale, q, c, nl, thb, ok, pmin, pmax);
   }
 }
 
+// Bit patterns of the pivot thresholds 16 FLT_EPSILON G[K][K] (G[K][K] is register K % 4 of
+// lane 16 (K / 4) + K), read onto the scalar unit.
 template <int K>
-__device__ __forceinline__ void read_diag(const float (&ar)[4], float (&gd)[16]) {
+__device__ __forceinline__ void read_thresholds(const float (&th)[4], int (&thb)[16]) {
   if constexpr (K < 16) {
-    gd[K] = uniform_read(ar[K & 3], 16 * (K >> 2) + K);
-    read_diag<K + 1>(ar, gd);
+    thb[K] = __builtin_amdgcn_readlane(__float_as_int(th[K & 3]), 16 * (K >> 2) + K);
+    read_thresholds<K + 1>(th, thb);
   }
 }
 
@@ -772,12 +782,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     ar[v] = in ? re + ((i == c) ? s2 : 0.f) : ((i == c) ? 1.f : 0.f);
     ai[v] = in ? acc_p[v] - pt : 0.f;
   }
-  float gd[16];
-  read_diag<0>(ar, gd);
+  int thb[16];
+  {
+    float th[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) th[v] = PivotRel<float>::v * ar[v];
+    read_thresholds<0>(th, thb);
+  }
   bool ok = true;
   float scale = 1.f;
   unsigned pmin = 0xFFFFFFFFu, pmax = 0u;
-  gj_all<0>(ar, ai, scale, q, c, NL, gd, ok, pmin, pmax);
+  gj_all<0>(ar, ai, scale, q, c, NL, thb, ok, pmin, pmax);
   // Subcarriers whose system is too ill-conditioned for FP32 (or not numerically positive
   // definite in FP32) are solved again in FP64 once the FP32 solution is done (the decision
   // is uniform over the wave; placed after the FP32 route, the FP64 route's registers do not
