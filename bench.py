@@ -183,6 +183,12 @@ def cpu_baseline(b, budget_s: float, reps: int = 5):
     return out
 
 
+def PRECISIONS(ranphy):
+    """The detector's precision modes: name, library code."""
+    return (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16), ("bf16", ranphy.PREC_BF16),
+            ("fp16_refined", ranphy.PREC_FP16_REFINED), ("bf16_refined", ranphy.PREC_BF16_REFINED))
+
+
 def detection_quality(torch, ranphy, synth):
     """Post-equalisation SINR of each detector precision and of the FP64 oracle on one slot
     per SNR point of the 64 x 16 workload (the same seeded slots as the batch's first 7)."""
@@ -201,8 +207,7 @@ def detection_quality(torch, ranphy, synth):
 
     ref = [sinr(xr[i], t["x"][i]) for i in range(sh.n_slots)]
     out = {}
-    for name, p in (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16),
-                    ("bf16", ranphy.PREC_BF16)):
+    for name, p in PRECISIONS(ranphy):
         hg = ranphy.chest_ls(sh, rx, pil)
         xg, _ = ranphy.mmse_detect(sh, rx, hg, nvar, precision=p)
         torch.cuda.synchronize()
@@ -605,8 +610,10 @@ def main():
     ap.add_argument("--batch-config", default=None, metavar="TILE_RE,BLOCKS_PER_CU",
                     help="batch workload: use this plan configuration instead of autotuning")
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"],
-                    help="input precision of the detector's Gram and matched filter")
+    ap.add_argument("--prec", default="fp32",
+                    choices=["fp32", "fp16", "bf16", "fp16_refined", "bf16_refined"],
+                    help="input precision of the detector's Gram and matched filter (the "
+                         "refined modes add one iterative-refinement step)")
     ap.add_argument("--path", default="auto", choices=["auto", "fused", "receive", "separate"],
                     help="fused detection + demapping (matrix-core shapes), the whole chain "
                          "in one launch (up to 8 layers) or three calls")
@@ -650,7 +657,7 @@ def main():
     t_gen = time.perf_counter() - t_gen
     shape = b["shape"]
     h_res = ranphy.H_PILOT if args.h_res == "pilot" else ranphy.H_FULL
-    prec = {"fp32": ranphy.PREC_FP32, "fp16": ranphy.PREC_FP16, "bf16": ranphy.PREC_BF16}[args.prec]
+    prec = dict(PRECISIONS(ranphy))[args.prec]
     print(f"# workload {args.workload}: {shape.n_slots} slots {shape.n_rx}x{shape.n_layers} "
           f"{shape.n_prb} PRB qm={shape.qm}; generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -769,7 +776,10 @@ def main():
         "value": value, "unit": "RE/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp16": "f16 products, f32 accumulate",
-                  "bf16": "bf16 products, f32 accumulate"}[args.prec], "data": "synthetic (seeded TDL exponential-PDP channel, Gray QAM, AWGN)",
+                  "bf16": "bf16 products, f32 accumulate",
+                  "fp16_refined": "f16 products, f32 accumulate, one f32-residual refinement",
+                  "bf16_refined": "bf16 products, f32 accumulate, one f32-residual refinement"
+                  }[args.prec], "data": "synthetic (seeded TDL exponential-PDP channel, Gray QAM, AWGN)",
         "config": {"workload": f"{shape.n_rx}Rx x {shape.n_layers}L, {shape.n_prb} PRB x {shape.n_symb} "
                                f"symbols, qm={shape.qm}, DMRS comb {shape.dmrs_comb} x TD {shape.dmrs_td}, "
                                f"{shape.n_slots} slots, h_res={args.h_res}, detector {args.prec}",
@@ -814,8 +824,7 @@ def main():
     if args.workload == "m" and h_res == ranphy.H_PILOT and not args.no_variants:
         variants = {}
         quality = detection_quality(torch, ranphy, synth)
-        for name, p in (("fp32", ranphy.PREC_FP32), ("fp16", ranphy.PREC_FP16),
-                        ("bf16", ranphy.PREC_BF16)):
+        for name, p in PRECISIONS(ranphy):
             for fz in (True, False):
                 key = name + ("" if fz else "_separate")
                 if p == prec and fz == fused:
@@ -843,7 +852,8 @@ def main():
             variants["learned_fp32"].update(learned_quality(torch, ranphy, synth, params, min_nv))
         out["variants"] = variants
         out["variants_note"] = ("Gram and matched filter with FP32 / FP16 / BF16 inputs (FP32 "
-                                "accumulation, FP32 inversion), demapping fused into the "
+                                "accumulation, FP32 inversion; _refined: plus one refinement "
+                                "step with the FP32 residual), demapping fused into the "
                                 "detector or (_separate) as its own pass; SINR = E|x|^2 / "
                                 "E|x~ - x|^2 against the transmitted symbols on one slot per "
                                 "SNR point (0..30 dB), loss relative to the FP64 oracle on the "

@@ -82,11 +82,24 @@ enum {
 };
 
 /* Input precision of the Gram and matched-filter products in ranphy_mmse_detect_prec.
- * Accumulation, inversion, solve and unbiasing are FP32 in every mode. */
+ * Accumulation, inversion, solve and unbiasing are FP32 in every mode.  FP16 operands are
+ * scaled per subcarrier by a power of two into the FP16 range before rounding and the
+ * products scaled back exactly, so any FP32 input magnitude works; within [2^-2, 2^14) no
+ * scaling happens (none is needed there).
+ * The refined modes add one step of iterative refinement (Sec. III-A: 16-bit components with
+ * the accuracy kept; the residual in FP32): each operand is also split into its 16-bit
+ * value and 16-bit remainder, the remainders give the FP32 Gram G and matched filter z to
+ * first order (G = G~ + dG, z = z~ + dz, products of 16-bit values accumulated in FP32), and
+ * the solution of the inverted 16-bit system G~ is corrected once with the FP32 residual,
+ * x^ <- x^ + G~^-1 (z - G x^); diag(G^-1), which the unbiasing uses, is corrected to the
+ * same order.  Their results approach the FP32 mode's (the remainders carry 22 bits in
+ * FP16, 16 in BF16). */
 enum {
-  RANPHY_PREC_FP32 = 0, /* FP32 inputs (the plain path; what ranphy_mmse_detect does)      */
-  RANPHY_PREC_FP16 = 1, /* inputs rounded to FP16, FP32 accumulation on the matrix cores  */
-  RANPHY_PREC_BF16 = 2  /* inputs rounded to BF16, FP32 accumulation on the matrix cores  */
+  RANPHY_PREC_FP32 = 0,         /* FP32 inputs (the plain path; ranphy_mmse_detect)        */
+  RANPHY_PREC_FP16 = 1,         /* inputs rounded to FP16, FP32 accumulation (matrix cores) */
+  RANPHY_PREC_BF16 = 2,         /* inputs rounded to BF16, FP32 accumulation (matrix cores) */
+  RANPHY_PREC_FP16_REFINED = 3, /* FP16 products plus one refinement step                   */
+  RANPHY_PREC_BF16_REFINED = 4  /* BF16 products plus one refinement step                   */
 };
 
 /* Buffer identifiers for ranphy_buffer_floats. */
@@ -149,7 +162,8 @@ RANPHY_API int ranphy_mmse_detect(const ranphy_slot_desc* d, const float* rx, co
  * reduced precision keeps detection accuracy (Sec. III-A: 16-bit real/imaginary parts are
  * often enough; Sec. IV, Fig. 5(a): single precision matches double), taken to 16-bit
  * matrix-core inputs.  Same arguments, layouts and outputs as ranphy_mmse_detect.
- * RANPHY_PREC_FP16 / RANPHY_PREC_BF16 run only on the matrix-core detector: one DMRS
+ * The 16-bit modes (RANPHY_PREC_FP16, _BF16 and their refined forms) run only on the
+ * matrix-core detector: one DMRS
  * occasion, 5..16 layers, n_rx a multiple of 16, rx / h / x / nv 16-byte aligned; other
  * shapes return RANPHY_ERR_UNSUPPORTED.  RANPHY_PREC_FP32 accepts every shape.
  */

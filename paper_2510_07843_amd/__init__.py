@@ -26,7 +26,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libranphy.so")
 
 H_PILOT, H_FULL = 0, 1
-PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
+PREC_FP32, PREC_FP16, PREC_BF16, PREC_FP16_REFINED, PREC_BF16_REFINED = 0, 1, 2, 3, 4
 OK, ERR_INVALID, ERR_UNSUPPORTED, ERR_LAUNCH = 0, -1, -2, -3
 BUF_RX, BUF_PILOTS, BUF_H, BUF_NOISE_VAR, BUF_X, BUF_NV, BUF_LLR = range(7)
 
@@ -204,7 +204,8 @@ def mmse_detect(shape, rx: torch.Tensor, h: torch.Tensor, noise_var: torch.Tenso
     """Unbiased LMMSE symbols and post-equalisation variances, [slot][dsym][sc][layer].
 
     ``precision`` selects the input precision of the Gram and matched-filter products
-    (PREC_FP32, PREC_FP16, PREC_BF16); the 16-bit modes need the matrix-core shapes."""
+    (PREC_FP32, PREC_FP16, PREC_BF16, and the refined PREC_FP16_REFINED, PREC_BF16_REFINED);
+    the 16-bit modes need the matrix-core shapes."""
     d = desc_of(shape)
     nx = buffer_floats(d, BUF_X)
     if x is None:

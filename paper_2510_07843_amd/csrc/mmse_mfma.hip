@@ -55,7 +55,16 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Precision of the Gram and matched-filter products (inputs; accumulation is always FP32).
-enum { kPrecF32 = 0, kPrecF16 = 1, kPrecBF16 = 2 };
+// The refined modes add one iterative-refinement step to the 16-bit products.
+enum { kPrecF32 = 0, kPrecF16 = 1, kPrecBF16 = 2, kPrecF16R = 3, kPrecBF16R = 4 };
+
+template <int PREC>
+struct Lowp {
+  static constexpr bool half = PREC == kPrecF16 || PREC == kPrecF16R;
+  static constexpr bool refine = PREC == kPrecF16R || PREC == kPrecBF16R;
+  using V = typename std::conditional<half, half8, bf16x8>::type;
+  using E = typename std::conditional<half, _Float16, __bf16>::type;
+};
 
 constexpr int kXcds = 8;
 // Condition estimate above which a subcarrier's system is solved again in FP64: the ratio
@@ -94,7 +103,7 @@ __device__ __forceinline__ V pack8(const float* v, float sign) {
 // the same element order, so the K ordering inside an instruction does not matter).
 template <typename V>
 struct LowpH {
-  V r[2], i[2], n[2];  // H real, imaginary, negated imaginary
+  V r[2], i[2];  // H real, imaginary
 };
 
 template <typename V, typename E>
@@ -104,9 +113,90 @@ __device__ __forceinline__ LowpH<V> pack_h(const float (&hr)[16], const float (&
   for (int t = 0; t < 2; ++t) {
     o.r[t] = pack8<V, E>(hr + 8 * t, 1.f);
     o.i[t] = pack8<V, E>(hi + 8 * t, 1.f);
-    o.n[t] = pack8<V, E>(hi + 8 * t, -1.f);
   }
   return o;
+}
+
+// The remainders of the same operands: x - (float)round16(x), rounded to the 16-bit type, so
+// that x = hi + lo to 22 (FP16) or 16 (BF16) significant bits.
+template <typename V, typename E>
+__device__ __forceinline__ V pack8_lo(const float* v) {
+  V r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (E)(v[e] - (float)(E)v[e]);
+  return r;
+}
+
+template <typename V, typename E>
+__device__ __forceinline__ LowpH<V> pack_h_lo(const float (&hr)[16], const float (&hi)[16]) {
+  LowpH<V> o;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    o.r[t] = pack8_lo<V, E>(hr + 8 * t);
+    o.i[t] = pack8_lo<V, E>(hi + 8 * t);
+  }
+  return o;
+}
+
+// A^H B of two channel operands (16 x 16 complex): the real part into re, the imaginary part
+// as the difference im_p - im_n of two FP32 sums (the 16-bit operands are not negated).
+template <typename V>
+__device__ __forceinline__ void herm_cross(const LowpH<V>& a, const LowpH<V>& b, floatx4& re,
+                                           floatx4& im_p, floatx4& im_n) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    re = mfma(a.r[t], b.r[t], re);
+    re = mfma(a.i[t], b.i[t], re);
+    im_p = mfma(a.r[t], b.i[t], im_p);
+    im_n = mfma(a.i[t], b.r[t], im_n);
+  }
+}
+
+// K step t of Z += A^H Y for a channel operand A and received samples packed as (br, bi),
+// with four products (no cancellation on top of the input rounding); Im Z = zi_p - zi_n.
+template <typename V>
+__device__ __forceinline__ void mf_step(const LowpH<V>& a, int t, const V& br, const V& bi,
+                                        floatx4& zr, floatx4& zi_p, floatx4& zi_n) {
+  zr = mfma(a.r[t], br, zr);
+  zr = mfma(a.i[t], bi, zr);
+  zi_p = mfma(a.r[t], bi, zi_p);
+  zi_n = mfma(a.i[t], br, zi_n);
+}
+
+// Largest magnitude over the wave of the 32 values a lane holds: a per-lane maximum, then
+// within each row of 16 lanes (DPP row_shr 1, 2, 4, 8; lanes without a source keep their
+// value) and across rows (row_bcast 15 into rows 1 and 3, row_bcast 31 into rows 2 and 3),
+// which leaves the wave's maximum in lane 63.  NaN is ignored (fmax).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_max(float v) {
+  return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(
+                      __float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false)));
+}
+__device__ __forceinline__ float wave_absmax(const float (&a)[16], const float (&b)[16]) {
+  float m = 0.f;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) m = fmaxf(m, fmaxf(fabsf(a[s]), fabsf(b[s])));
+  m = dpp_max<0x111, 0xF>(m);
+  m = dpp_max<0x112, 0xF>(m);
+  m = dpp_max<0x114, 0xF>(m);
+  m = dpp_max<0x118, 0xF>(m);
+  m = dpp_max<0x142, 0xA>(m);
+  m = dpp_max<0x143, 0xC>(m);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(m), 63));
+}
+
+// FP16 operands are scaled by a power of two 2^e before rounding, e chosen from the wave's
+// largest magnitude m so that m * 2^e lies in [2^13, 2^14).  Without refinement the scale is
+// only applied when m lies outside [2^-2, 2^14) (e = 0 there: every operand then rounds to a
+// normal FP16 value or is negligible against m); the refined modes always apply it, so that
+// the remainders (2^-11 of their values) stay normal too.  A power of two commutes with every
+// rounding while values stay normal, so scaled products, scaled back exactly, equal the
+// unscaled ones wherever those are in range.  m = 0, infinite or NaN: e = 0.
+template <bool ALWAYS>
+__device__ __forceinline__ int f16_scale_exp(float m) {
+  if (!(m > 0.f) || m > FLT_MAX) return 0;
+  const int e = __builtin_amdgcn_frexp_expf(m) - 1;  // m in [2^e, 2^(e+1))
+  return (!ALWAYS && e >= -2 && e < 14) ? 0 : 13 - e;
 }
 
 template <typename V>
@@ -116,21 +206,6 @@ __device__ __forceinline__ void gram_lowp(const LowpH<V>& a, floatx4& acc_g, flo
     acc_g = mfma(a.r[t], a.r[t], acc_g);
     acc_g = mfma(a.i[t], a.i[t], acc_g);
     acc_p = mfma(a.r[t], a.i[t], acc_p);
-  }
-}
-
-// Z = H^H Y with four products (no cancellation on top of the input rounding).
-template <typename V, typename E>
-__device__ __forceinline__ void mf_lowp(const LowpH<V>& a, const float (&yr)[16],
-                                        const float (&yi)[16], floatx4& zr, floatx4& zi) {
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const V b_r = pack8<V, E>(yr + 8 * t, 1.f);
-    const V b_i = pack8<V, E>(yi + 8 * t, 1.f);
-    zr = mfma(a.r[t], b_r, zr);
-    zr = mfma(a.i[t], b_i, zr);
-    zi = mfma(a.r[t], b_i, zi);
-    zi = mfma(a.n[t], b_r, zi);
   }
 }
 
@@ -213,6 +288,28 @@ __device__ __forceinline__ float2 bfp_sample(const unsigned* __restrict__ words,
   const int e = (int)b[0];
   return make_float2(ldexpf((float)((int)((unsigned)f << 23) >> 23), e),
                      ldexpf((float)((int)((unsigned)(f >> 9) << 23) >> 23), e));
+}
+
+// OUT = P^H Q for 16 x 16 complex P, Q held as lane (q, c) <- row 4q + s of column c in
+// register s (P^H Q = P Q for a Hermitian P): the accumulator layout of P, conjugated, is
+// the A-operand layout of P^H (A[c][4q+s] = conj(P[4q+s][c])) and the accumulator layout of
+// Q is the B-operand layout.  Three real products:
+//   Re = pr qr + pi qi,  Im = (pr - pi)(qr + qi) - pr qr + pi qi.
+__device__ __forceinline__ void herm_mul(const float (&pr)[4], const float (&pi)[4],
+                                         const floatx4& qr, const floatx4& qi, floatx4& outr,
+                                         floatx4& outi) {
+  floatx4 n1 = {0.f, 0.f, 0.f, 0.f}, n2 = n1, n3 = n1;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    n1 = mfma(pr[s], qr[s], n1);
+    n2 = mfma(pi[s], qi[s], n2);
+    n3 = mfma(pr[s] - pi[s], qr[s] + qi[s], n3);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    outr[v] = n1[v] + n2[v];
+    outi[v] = n3[v] - n1[v] + n2[v];
+  }
 }
 
 // dst += (src0 of lane K of the lane's row of 16) * src1; K is asm operand 10.
@@ -552,7 +649,7 @@ __device__ __forceinline__ void emit_llr(float* __restrict__ llr, float* stage, 
 }
 
 template <int HRES, int NL, int PREC, int RXF, int LSF>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Lowp<PREC>::refine ? 3 : 5, 8))) mmse_mfma_kernel(Geom g, const float2* __restrict__ rx,
                                                         const float2* __restrict__ h,
                                                         const float2* __restrict__ pil,
                                                         const float* __restrict__ nvar,
@@ -746,8 +843,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
   // below).  16-bit inputs: acc_g = Hr^T Hr + Hi^T Hi and P directly (no difference of the
   // rounded operands).
   floatx4 acc_g = {0.f, 0.f, 0.f, 0.f}, acc_p = acc_g, z_r = acc_g, z_i = acc_g;
-  LowpH<half8> h16;
-  LowpH<bf16x8> hb16;
+  using LV = typename Lowp<PREC>::V;
+  using LE = typename Lowp<PREC>::E;
+  LowpH<LV> hh, hl;      // 16-bit channel operands and (refined modes) their remainders
+  floatx4 dg_r = acc_g, dg_i = acc_g;  // refined modes: H_hi^H H_lo + H_lo^H H_hi
+  int eh = 0;            // FP16: the channel operands' power-of-two scale
   if constexpr (PREC == kPrecF32) {
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
@@ -755,12 +855,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
       acc_g = mfma(hd, hd, acc_g);
       acc_p = mfma(hr[s], hi[s], acc_p);
     }
-  } else if constexpr (PREC == kPrecF16) {
-    h16 = pack_h<half8, _Float16>(hr, hi);
-    gram_lowp(h16, acc_g, acc_p);
   } else {
-    hb16 = pack_h<bf16x8, __bf16>(hr, hi);
-    gram_lowp(hb16, acc_g, acc_p);
+    if constexpr (Lowp<PREC>::half) {
+      eh = f16_scale_exp<Lowp<PREC>::refine>(wave_absmax(hr, hi));
+      if (eh != 0) {
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+          hr[s] = ldexpf(hr[s], eh);
+          hi[s] = ldexpf(hi[s], eh);
+        }
+      }
+    }
+    hh = pack_h<LV, LE>(hr, hi);
+    gram_lowp(hh, acc_g, acc_p);
+    if constexpr (Lowp<PREC>::refine) hl = pack_h_lo<LV, LE>(hr, hi);
+    if (eh != 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc_g[v] = ldexpf(acc_g[v], -2 * eh);
+        acc_p[v] = ldexpf(acc_p[v], -2 * eh);
+      }
+    }
   }
 
   // ---- 4. G = Re + j (P - P^T) + s2 I, padded layers -> identity; invert in place ---------
@@ -842,37 +957,108 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
           z_r[v] = acc_m1[v] + acc_m2[v];
           z_i[v] = acc_m1[v] - acc_m2[v] - acc_m3[v];
         }
-      } else if constexpr (PREC == kPrecF16) {
-        mf_lowp<half8, _Float16>(h16, yr, yi, z_r, z_i);
       } else {
-        mf_lowp<bf16x8, __bf16>(hb16, yr, yi, z_r, z_i);
+        int ey = 0;  // FP16: the samples' power-of-two scale
+        if constexpr (Lowp<PREC>::half) {
+          ey = f16_scale_exp<Lowp<PREC>::refine>(wave_absmax(yr, yi));
+          if (ey != 0) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+              yr[s] = ldexpf(yr[s], ey);
+              yi[s] = ldexpf(yi[s], ey);
+            }
+          }
+        }
+        // One K step at a time (8 antennas per lane), so that few packed samples are live.
+        // Refined modes: H^H y of the FP32 operands to first order, Z~ + H_hi^H y_lo +
+        // H_lo^H y_hi.
+        floatx4 zi_n = z_i;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const LV br = pack8<LV, LE>(yr + 8 * t, 1.f);
+          const LV bi = pack8<LV, LE>(yi + 8 * t, 1.f);
+          mf_step(hh, t, br, bi, z_r, z_i, zi_n);
+          if constexpr (Lowp<PREC>::refine) {
+            mf_step(hh, t, pack8_lo<LV, LE>(yr + 8 * t), pack8_lo<LV, LE>(yi + 8 * t), z_r, z_i,
+                    zi_n);
+            mf_step(hl, t, br, bi, z_r, z_i, zi_n);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) z_i[v] -= zi_n[v];
+        if (eh + ey != 0) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            z_r[v] = ldexpf(z_r[v], -(eh + ey));
+            z_i[v] = ldexpf(z_i[v], -(eh + ey));
+          }
+        }
+        if constexpr (Lowp<PREC>::refine) {
+          // The Gram of the FP32 operands to first order: H^H H = G~ + dG + (H_lo^H H_lo)
+          // (formed here rather than before the inversion: fewer registers live across it).
+          floatx4 dg_n = dg_i;
+          herm_cross(hh, hl, dg_r, dg_i, dg_n);
+          herm_cross(hl, hh, dg_r, dg_i, dg_n);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            // padded layers (copies of layer NL-1) carry an identity block: no correction
+            const bool in = (4 * q + v < NL) && (c < NL);
+            dg_r[v] = in ? ldexpf(dg_r[v], -2 * eh) : 0.f;
+            dg_i[v] = in ? ldexpf(dg_i[v] - dg_n[v], -2 * eh) : 0.f;
+          }
+        }
       }
     }
 
-    // ---- 6. X_hat = G^-1 Z on the matrix cores -------------------------------------------
-    // A[i = c][m = 4q + s] = G^-1[c][4q+s] = conj(G^-1[4q+s][c]) = (ar[s], -ai[s]);
-    // B[m = 4q + s][d = c] = Z[4q+s][c].
-    // Three real products again: Re = ar zr + ai zi,  Im = (ar - ai)(zr + zi) - ar zr + ai zi.
-    floatx4 acc_n1 = {0.f, 0.f, 0.f, 0.f}, acc_n2 = acc_n1, acc_n3 = acc_n1;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const float zr = z_r[s];
-      const float zi = z_i[s];
-      acc_n1 = mfma(ar[s], zr, acc_n1);
-      acc_n2 = mfma(ai[s], zi, acc_n2);
-      acc_n3 = mfma(ar[s] - ai[s], zr + zi, acc_n3);
-    }
+    // ---- 6. X_hat = G^-1 Z on the matrix cores (G^-1 Hermitian) --------------------------
     floatx4 acc_xr, acc_xi;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      acc_xr[v] = acc_n1[v] + acc_n2[v];
-      acc_xi[v] = acc_n3[v] - acc_n1[v] + acc_n2[v];
-    }
+    herm_mul(ar, ai, z_r, z_i, acc_xr, acc_xi);
 
     // ---- 7. unbias: lane (q, d = c) holds layers 4q .. 4q+3 of data symbol d ------------
     float dl[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) dl[v] = lane_read(ar[v], 16 * q + 4 * q + v);  // G^-1[4q+v][4q+v]
+    if constexpr (Lowp<PREC>::refine) {
+      // One refinement step.  With G~ the 16-bit Gram (+ s2 I) that was inverted and
+      // G = G~ + dG the Gram of the FP32 operands, the residual of x^ = G~^-1 Z is
+      // Z - G x^ = -dG x^ (Z already the FP32 matched filter to first order), so
+      //   x^ <- x^ - G~^-1 dG x^   and, to the same order,   diag(G^-1) = diag(G~^-1) -
+      //   diag(G~^-1 dG G~^-1).   With N = dG G~^-1 (dG Hermitian), G~^-1 dG = N^H.
+      floatx4 nr, ni, cr, ci;
+      float dgr[4], dgi[4], nrr[4], nri[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        dgr[v] = dg_r[v];
+        dgi[v] = dg_i[v];
+      }
+      floatx4 gr, gi;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        gr[v] = ar[v];
+        gi[v] = ai[v];
+      }
+      herm_mul(dgr, dgi, gr, gi, nr, ni);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        nrr[v] = nr[v];
+        nri[v] = ni[v];
+      }
+      herm_mul(nrr, nri, acc_xr, acc_xi, cr, ci);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc_xr[v] -= cr[v];
+        acc_xi[v] -= ci[v];
+      }
+      // diag(N^H G~^-1)[l] = sum_n conj(N[n][l]) G~^-1[n][l]: column l of both, which lanes
+      // (q, c = l) hold in rows 4q..4q+3; summed over the four row groups.
+      float part = 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) part = fmaf(nrr[v], ar[v], fmaf(nri[v], ai[v], part));
+      part += lane_read(part, lane ^ 32);
+      part += lane_read(part, lane ^ 16);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dl[v] -= lane_read(part, 16 * q + 4 * q + v);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const float sd = s2 * dl[v];
@@ -923,7 +1109,7 @@ template <int HRES, int NL, int PREC>
 void launch_one(const Geom& g, dim3 grid, const float2* rx, bool bfp, const float2* h,
                 const float2* pil, const float* nvar, float2* x, float* nv, float* llr,
                 hipStream_t s) {
-  if constexpr (HRES == 0) {
+  if constexpr (HRES == 0 && PREC == kPrecF32) {  // the one-launch chain is FP32 only
     if (pil != nullptr) {
       if (bfp)
         hipLaunchKernelGGL((mmse_mfma_kernel<0, NL, PREC, 1, 1>), grid, dim3(256), 0, s, g, rx,
@@ -988,10 +1174,13 @@ hipError_t launch_mmse_mfma(const Geom& g, const float2* rx, bool bfp, const flo
   const int64_t waves = (int64_t)g.n_slots * g.n_sc;
   const int64_t blocks = (waves + 3) / 4;
   const dim3 grid((unsigned)((blocks + kXcds - 1) / kXcds * kXcds));
+  if (pil != nullptr && prec != kPrecF32) return hipErrorInvalidValue;  // one launch: FP32 only
   switch (prec) {
     case kPrecF32: launch_prec<kPrecF32>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
     case kPrecF16: launch_prec<kPrecF16>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
     case kPrecBF16: launch_prec<kPrecBF16>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
+    case kPrecF16R: launch_prec<kPrecF16R>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
+    case kPrecBF16R: launch_prec<kPrecBF16R>(g, grid, rx, bfp, h, pil, h_res, nvar, x, nv, llr, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

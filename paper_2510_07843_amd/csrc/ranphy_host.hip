@@ -98,6 +98,11 @@ int make_geom(const ranphy_slot_desc* d, Geom* g) {
 
 bool aligned8(const void* p) { return p != nullptr && ((uintptr_t)p & 7u) == 0; }
 
+bool precision_valid(int p) {
+  return p == RANPHY_PREC_FP32 || p == RANPHY_PREC_FP16 || p == RANPHY_PREC_BF16 ||
+         p == RANPHY_PREC_FP16_REFINED || p == RANPHY_PREC_BF16_REFINED;
+}
+
 int status_of(hipError_t e) { return e == hipSuccess ? RANPHY_OK : RANPHY_ERR_LAUNCH; }
 
 }  // namespace
@@ -175,9 +180,7 @@ int ranphy_mmse_detect_prec(const ranphy_slot_desc* d, const float* rx, const fl
   const int rc = ranphy::make_geom(d, &g);
   if (rc) return rc;
   if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
-  if (precision != RANPHY_PREC_FP32 && precision != RANPHY_PREC_FP16 &&
-      precision != RANPHY_PREC_BF16)
-    return RANPHY_ERR_INVALID;
+  if (!ranphy::precision_valid(precision)) return RANPHY_ERR_INVALID;
   if (g.n_slots == 0) return RANPHY_OK;
   if (!ranphy::aligned8(rx) || !ranphy::aligned8(h) || !ranphy::aligned8(x) ||
       !ranphy::aligned8(nv) || noise_var == nullptr || ((uintptr_t)noise_var & 3u))
@@ -214,9 +217,7 @@ int ranphy_mmse_llr(const ranphy_slot_desc* d, const float* rx, const float* h, 
   const int rc = ranphy::make_geom(d, &g);
   if (rc) return rc;
   if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
-  if (precision != RANPHY_PREC_FP32 && precision != RANPHY_PREC_FP16 &&
-      precision != RANPHY_PREC_BF16)
-    return RANPHY_ERR_INVALID;
+  if (!ranphy::precision_valid(precision)) return RANPHY_ERR_INVALID;
   if (g.n_slots == 0) return RANPHY_OK;
   if ((x == nullptr) != (nv == nullptr)) return RANPHY_ERR_INVALID;
   if (!ranphy::aligned8(rx) || !ranphy::aligned8(h) || !ranphy::aligned8(llr) ||
@@ -237,9 +238,7 @@ int ranphy_mmse_llr_bfp(const ranphy_slot_desc* d, const uint32_t* packed, const
   const int rc = ranphy::make_geom(d, &g);
   if (rc) return rc;
   if (h_res != RANPHY_H_PILOT && h_res != RANPHY_H_FULL) return RANPHY_ERR_INVALID;
-  if (precision != RANPHY_PREC_FP32 && precision != RANPHY_PREC_FP16 &&
-      precision != RANPHY_PREC_BF16)
-    return RANPHY_ERR_INVALID;
+  if (!ranphy::precision_valid(precision)) return RANPHY_ERR_INVALID;
   if (g.n_slots == 0) return RANPHY_OK;
   if ((x == nullptr) != (nv == nullptr)) return RANPHY_ERR_INVALID;
   if (!ranphy::aligned8(packed) || !ranphy::aligned8(h) || !ranphy::aligned8(llr) ||

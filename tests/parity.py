@@ -277,3 +277,40 @@ def rounding_bound(Hsc, y, xt, nv, s2, u):
         bx = (ex[:, None] + np.abs(xt) * dmu) / (mu - dmu)
         bv = dmu / (mu * (mu - dmu))
     return bx, bv, valid
+
+
+def refined_bound(Hsc, y, xt, nv, s2, p):
+    """Per (RE, layer) bound on |x~(refined 16-bit mode) - x~(exact inputs)| and on the
+    variance, for the one-step refinement of the 16-bit detector (without FP32 rounding,
+    which the caller adds).  Each value is split into a p-bit part (error u1 = 2^-p of its
+    magnitude) and a p-bit remainder (what is left, u2 = 2^-2p).  With A = G~ + s2 I the
+    inverted 16-bit system, dG the first-order Gram correction, dZ (resp. dG2) what the
+    split leaves out of the matched filter (resp. the Gram), E = A^-1 (dG + dG2) and x* the
+    exact solution, the refined x^ differs from x* by
+        -A^-1 dZ + A^-1 dG A^-1 dZ + A^-1 dG2 (I + E) x* - E^2 x*
+    and diag(A^-1 - A^-1 dG A^-1) from diag(G^-1) by at most ||dG2|| / lA^2 + ||E||^2 / l,
+    so with ||dG|| <= u1 nF (2 n2 + u1 nF), ||dG2|| <= u1^2 nF^2 + u2 nF (2 n2 + 2 u1 nF +
+    u2 nF), ||dZ|| <= (u1^2 nF + u2 (2 nF + n2 + u1 nF)) ||y|| (nF, n2: Frobenius and
+    spectral norms of H; l = lmin(G + s2 I), lA >= l - ||dG|| - ||dG2||).  Returns
+    (bx [n][nl], bv [n][nl], valid [n]) as rounding_bound does."""
+    u1, u2 = 2.0 ** -p, 2.0 ** (-2 * p)
+    nF = np.linalg.norm(Hsc, axis=(1, 2))
+    n2 = np.linalg.norm(Hsc, ord=2, axis=(1, 2))
+    ny = np.linalg.norm(y, axis=1)
+    G = np.einsum("nrl,nrm->nlm", Hsc.conj(), Hsc) + s2[:, None, None] * np.eye(Hsc.shape[2])
+    lam = np.linalg.eigvalsh(G)[:, 0]
+    eD = u1 * nF * (2 * n2 + u1 * nF)
+    eD2 = u1 ** 2 * nF ** 2 + u2 * nF * (2 * n2 + 2 * u1 * nF + u2 * nF)
+    ez = (u1 ** 2 * nF + u2 * (2 * nF + n2 + u1 * nF)) * ny
+    lA = lam - eD - eD2
+    E = (eD + eD2) / lA
+    mu = 1.0 / (1.0 + nv)
+    xs = np.linalg.norm(xt * mu, axis=1)  # ||x^*|| (biased solution)
+    ex = ez * (1.0 + eD / lA) / lA + eD2 * (1.0 + E) * xs / lA + E ** 2 * xs
+    dd = eD2 / lA ** 2 + E ** 2 / lam
+    dmu = s2[:, None] * dd[:, None]
+    valid = (lA > 0) & (E < 1) & np.all(mu > dmu, axis=1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        bx = (ex[:, None] + np.abs(xt) * dmu) / (mu - dmu)
+        bv = dmu / (mu * (mu - dmu))
+    return bx, bv, valid

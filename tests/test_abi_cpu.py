@@ -188,6 +188,10 @@ def test_fused_detect_demap_validation(L):
     assert L.ranphy_mmse_llr(ctypes.byref(d2), a, a, 0, a, None, None, a, 0, None) == -2
     d3 = _desc(n_rx=16, n_layers=4)
     assert L.ranphy_mmse_llr(ctypes.byref(d3), a, a, 0, a, a, a, a, 1, None) == -2
+    # the refined 16-bit modes (3, 4) are matrix-core modes too
+    for prec in (3, 4):
+        assert L.ranphy_mmse_llr(ctypes.byref(d3), a, a, 0, a, a, a, a, prec, None) == -2
+        assert L.ranphy_mmse_detect_prec(ctypes.byref(d3), a, a, 0, a, a, a, prec, None) == -2
 
 
 def test_batch_plan_validation(L):
@@ -297,7 +301,7 @@ def test_fused_bfp_validation(L):
                                  0, None) == -1  # words not 8-byte aligned
     assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(16), 0, P(16), P(16), None, P(16), 0,
                                  None) == -1  # x without nv
-    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(16), 0, P(16), None, None, P(16), 3,
+    assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(16), 0, P(16), None, None, P(16), 5,
                                  None) == -1  # precision
     assert L.ranphy_mmse_llr_bfp(ctypes.byref(m), P(16), P(0x1008), 0, P(16), None, None, P(16),
                                  0, None) == -2  # channel not 16-byte aligned: not the MFMA form
