@@ -474,7 +474,7 @@ def bench_batch(args, torch, ranphy, synth):
         tile, bpc = (int(v) for v in args.batch_config.split(","))
         tuned = tune.autotune(ues, tiles=(tile,), blocks_per_cu=(bpc,), reps=1)
     else:
-        tuned = tune.autotune(ues, reps=3)
+        tuned = tune.autotune(ues, reps=3, cache=args.tune_cache)
     b, nb = tuned["batch"], tuned["n_blocks"]
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -566,6 +566,7 @@ def bench_batch(args, torch, ranphy, synth):
                                f"QPSK..256QAM, SNR 0..30 dB; one persistent launch, HIP graph",
                    "ues": len(ues), "data_re_per_step": re, "path": "batch_persistent_fp32",
                    "work_items": b.n_items, "tile_re": tuned["tile_re"],
+                   "autotune_cached": tuned.get("cached", False),
                    "blocks": nb, "data_seconds": round(t_gen, 1)},
         "kernels_ms": {"batch_kernel": ms},
         "roofline": roof,
@@ -609,6 +610,9 @@ def main():
     ap.add_argument("--slots", type=int, default=None, help="override the batch size")
     ap.add_argument("--batch-config", default=None, metavar="TILE_RE,BLOCKS_PER_CU",
                     help="batch workload: use this plan configuration instead of autotuning")
+    ap.add_argument("--tune-cache", default=None, metavar="JSON",
+                    help="batch workload: autotune cache file (a batch class in it is not "
+                         "timed again)")
     ap.add_argument("--h-res", default="pilot", choices=["pilot", "full"])
     ap.add_argument("--prec", default="fp32",
                     choices=["fp32", "fp16", "bf16", "fp16_refined", "bf16_refined"],

@@ -32,6 +32,12 @@ class RefDesc(ctypes.Structure):
     ]
 
 
+SAN_LIB_PATH = os.path.join(_HERE, "libranphy_ref_san.so")
+# Set to the sanitized library's path (with the sanitizer runtimes preloaded) to run the
+# oracle's checks under AddressSanitizer and UndefinedBehaviorSanitizer.
+LIB_ENV = "RANPHY_REF_LIB"
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
     if force or not os.path.exists(LIB_PATH):
@@ -42,15 +48,30 @@ def build(force: bool = True) -> str:
     return LIB_PATH
 
 
+def build_sanitized() -> str:
+    """The same oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (every
+    undefined-behaviour finding fatal), without OpenMP (one thread: the sanitizers then see
+    one deterministic order of the loops).  Load it by setting RANPHY_REF_LIB to its path,
+    with libasan and libubsan preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", "-o", SAN_LIB_PATH + ".tmp", SRC_PATH, "-lm"]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(SAN_LIB_PATH + ".tmp", SAN_LIB_PATH)
+    return SAN_LIB_PATH
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        path = os.environ.get(LIB_ENV) or LIB_PATH
+        if path == LIB_PATH and (not os.path.exists(LIB_PATH) or
+                                 os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)):
             build()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         D = ctypes.POINTER(RefDesc)
         L.ranphy_ref_chest_ls.argtypes = [D, P, P, P, ctypes.c_int]

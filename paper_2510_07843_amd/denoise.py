@@ -7,7 +7,10 @@ tensors on the GPU (one slot = one group of rx * layer images over an occasion x
 """
 from __future__ import annotations
 
+import hashlib
+import json
 import math
+import os
 import time
 from typing import Dict, Optional, Sequence
 
@@ -35,28 +38,144 @@ def init_params(seed: int, device="cuda") -> torch.Tensor:
     return torch.from_numpy(v).to(device)
 
 
+# ---- checkpoints ---------------------------------------------------------------------------
+# One file: a JSON header on the first line, then the binary sections it lists, each a flat
+# little-endian array at the byte offset given (relative to the end of the header line):
+#   params_bf16  the parameters rounded to BF16 (round to nearest even): the compact form the
+#                network's convolutions use (weights are packed to BF16 for the matrix cores;
+#                biases are FP32 in the kernels, so inference from this blob alone differs
+#                from params_f32 by the biases' rounding);
+#   params_f32   the FP32 parameters;  adam_m, adam_v  the Adam moments (FP32).
+# The header carries the format name and version, the parameter count and layout, the step,
+# the training state needed to resume (learning rate, total steps, batch, seed, the state of
+# the minibatch stream, the losses so far), optional extra fields, and the SHA-256 of the
+# binary part, checked on load.
+CKPT_FORMAT = "ranphy-cnn-checkpoint"
+CKPT_VERSION = 1
+
+
+def bf16_bits(v: np.ndarray) -> np.ndarray:
+    """FP32 values rounded to BF16 (nearest, ties to even), as uint16 bit patterns; NaN stays
+    a quiet NaN."""
+    u = np.ascontiguousarray(v, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    nan = np.isnan(np.asarray(v, np.float32))
+    r[nan] = ((u[nan] >> 16) | 0x40).astype(np.uint16)
+    return r
+
+
+def save_checkpoint(path: str, params: torch.Tensor, m: Optional[torch.Tensor] = None,
+                    v: Optional[torch.Tensor] = None, step: int = 0,
+                    train_state: Optional[Dict] = None, extra: Optional[Dict] = None) -> None:
+    """Write the parameters (BF16 and FP32), the Adam moments if given and the training state
+    to `path` (written to a temporary file, then renamed)."""
+    p32 = params.detach().float().cpu().numpy().ravel()
+    n = p32.size
+    if n != cnn_param_count():
+        raise ValueError(f"{n} parameters, expected {cnn_param_count()}")
+    blobs = [("params_bf16", "bf16", bf16_bits(p32).tobytes()), ("params_f32", "f32", p32.tobytes())]
+    for name, t in (("adam_m", m), ("adam_v", v)):
+        if t is not None:
+            blobs.append((name, "f32", t.detach().float().cpu().numpy().ravel().tobytes()))
+    sections, off, h = [], 0, hashlib.sha256()
+    for name, dt, b in blobs:
+        sections.append(dict(name=name, dtype=dt, count=n, offset=off, bytes=len(b)))
+        off += len(b)
+        h.update(b)
+    header = dict(format=CKPT_FORMAT, version=CKPT_VERSION, param_count=n,
+                  layout="per layer l = 0..3: W_l[9][32 in][32 out] then b_l[32]",
+                  channels=list(CHANNELS), step=int(step), sections=sections,
+                  sha256=h.hexdigest(), train_state=train_state or {}, extra=extra or {})
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as f:
+        f.write(json.dumps(header).encode() + b"\n")
+        for _, _, b in blobs:
+            f.write(b)
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str, device="cuda") -> Dict:
+    """Read a checkpoint: params (FP32, from params_f32, else the BF16 blob widened), m and v
+    (None when absent), params_bf16 (uint16 array), step, train_state and extra.  Raises on a
+    wrong format, version, size or checksum."""
+    with open(path, "rb") as f:
+        header = json.loads(f.readline().decode())
+        body = f.read()
+    if header.get("format") != CKPT_FORMAT or header.get("version") != CKPT_VERSION:
+        raise ValueError(f"{path}: not a {CKPT_FORMAT} v{CKPT_VERSION} file")
+    if hashlib.sha256(body).hexdigest() != header["sha256"]:
+        raise ValueError(f"{path}: checksum mismatch")
+    n = header["param_count"]
+    if n != cnn_param_count():
+        raise ValueError(f"{path}: {n} parameters, the library has {cnn_param_count()}")
+    sec = {d["name"]: d for d in header["sections"]}
+
+    def arr(name):
+        d = sec.get(name)
+        if d is None:
+            return None
+        raw = body[d["offset"]:d["offset"] + d["bytes"]]
+        if d["dtype"] == "bf16":
+            return np.frombuffer(raw, np.uint16).copy()
+        return np.frombuffer(raw, np.float32).copy()
+
+    bf = arr("params_bf16")
+    p32 = arr("params_f32")
+    if p32 is None:
+        p32 = (bf.astype(np.uint32) << 16).view(np.float32)
+    dev = lambda a: None if a is None else torch.from_numpy(a).to(device)  # noqa: E731
+    return dict(params=dev(p32), m=dev(arr("adam_m")), v=dev(arr("adam_v")), params_bf16=bf,
+                step=header["step"], train_state=header["train_state"], extra=header["extra"])
+
+
 def _as_groups(h: torch.Tensor, n_slots: int) -> torch.Tensor:
     return torch.view_as_real(h.reshape(-1)).reshape(n_slots, -1)
 
 
 def train(h_est: torch.Tensor, h_true: torch.Tensor, noise_var: torch.Tensor, n_slots: int,
           rows: int, cols: int, n_img: int, steps: int = 300, batch: int = 4, lr: float = 2e-3,
-          seed: int = 0, params: Optional[torch.Tensor] = None) -> Dict:
+          seed: int = 0, params: Optional[torch.Tensor] = None, resume: Optional[str] = None,
+          checkpoint: Optional[str] = None, checkpoint_every: int = 0,
+          stop_after: Optional[int] = None, on_step=None) -> Dict:
     """Adam on the noise-normalised MSE between the refined and the true channel at the
     pilots; mini-batches of `batch` slots drawn without replacement per step from a seeded
-    stream, cosine-decayed learning rate.  Returns the parameters, the loss of every 10th step
-    and the time."""
+    stream, cosine-decayed learning rate over `steps`.  Returns the parameters, the loss of
+    every 10th step and the time.
+
+    resume: a checkpoint written by this function: parameters, Adam moments, the minibatch
+    stream and the losses continue from its step, so that the resumed run's parameters equal
+    an uninterrupted run's bit for bit (the library's training kernels are deterministic).
+    checkpoint / checkpoint_every: write one every that many steps (and after the last step).
+    stop_after: end after that step (a run interrupted there, for checkpoint tests).
+    on_step(step, params): called after every update (validation curves)."""
     dev = h_est.device
     x_all, t_all = _as_groups(h_est, n_slots), _as_groups(h_true, n_slots)
-    p = init_params(seed, dev) if params is None else params
-    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([0xC23, seed])))
+    losses, first = [], 1
+    if resume is not None:
+        ck = load_checkpoint(resume, dev)
+        st = ck["train_state"]
+        if (st.get("steps"), st.get("batch"), st.get("lr"), st.get("seed")) != (steps, batch, lr, seed):
+            raise ValueError("resume: steps, batch, lr and seed must match the checkpoint's")
+        p, m, v = ck["params"], ck["m"], ck["v"]
+        rng.bit_generator.state = st["rng_state"]
+        losses = [torch.tensor(l) for l in st["losses"]]
+        first = ck["step"] + 1
+    else:
+        p = init_params(seed, dev) if params is None else params
+        m, v = torch.zeros_like(p), torch.zeros_like(p)
     ws = torch.empty(cnn_workspace_bytes(rows, cols, n_img, batch, True), dtype=torch.uint8,
                      device=dev)
-    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([0xC23, seed])))
-    losses = []
+
+    def save(step):
+        save_checkpoint(checkpoint, p, m, v, step, dict(
+            steps=steps, batch=batch, lr=lr, seed=seed, rng_state=rng.bit_generator.state,
+            losses=[float(l.item()) for l in losses]))
+
+    last = steps if stop_after is None else min(steps, stop_after)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for step in range(1, steps + 1):
+    for step in range(first, last + 1):
         idx = torch.from_numpy(rng.choice(n_slots, batch, replace=False)).to(dev)
         xb = x_all.index_select(0, idx).reshape(-1).contiguous()
         tb = t_all.index_select(0, idx).reshape(-1).contiguous()
@@ -66,10 +185,14 @@ def train(h_est: torch.Tensor, h_true: torch.Tensor, noise_var: torch.Tensor, n_
         cnn_adam(p, grad, m, v, step, rate)
         if step % 10 == 0:
             losses.append(loss)
+        if on_step is not None:
+            on_step(step, p)
+        if checkpoint and ((checkpoint_every and step % checkpoint_every == 0) or step == last):
+            save(step)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dict(params=p, losses=[float(l.item()) for l in losses], seconds=dt, steps=steps,
-                batch=batch, images_per_step=batch * n_img)
+                batch=batch, images_per_step=batch * n_img, last_step=last)
 
 
 def nmse_db(est: torch.Tensor, true: torch.Tensor) -> float:

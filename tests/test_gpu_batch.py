@@ -125,3 +125,28 @@ def test_autotune_returns_a_valid_configuration():
     torch.cuda.synchronize()
     for u, r in zip(ues, ref):
         assert torch.equal(u["llr"].view(torch.int32), r.view(torch.int32))
+
+
+def test_autotune_cache_times_a_class_once(tmp_path):
+    # The first batch of a class is timed and stored; a second batch of the same class (the
+    # same UE kinds, another order and PRB split) is planned from the cache untimed, and its
+    # LLRs equal those of the same plan built directly.
+    f = str(tmp_path / "tune.json")
+    ues = make_ues(8, seed=4, max_prb=32)
+    first = tune.autotune(ues, tiles=(256, 512), blocks_per_cu=(1, 2), reps=2, cache=f)
+    assert not first["cached"]
+    again = [dict(u) for u in reversed(ues)]
+    for u in again:
+        u.pop("llr", None)
+    second = tune.autotune(again, tiles=(256, 512), blocks_per_cu=(1, 2), reps=2, cache=f)
+    assert second["cached"]
+    assert (second["tile_re"], second["blocks_per_cu"]) == (first["tile_re"], first["blocks_per_cu"])
+    second["batch"].run(second["n_blocks"])
+    got = [u["llr"].clone() for u in again]
+    for u in again:
+        u["llr"] = None
+    direct = ranphy.Batch(again, tile_re=second["tile_re"])
+    direct.run(second["n_blocks"])
+    torch.cuda.synchronize()
+    for a, u in zip(got, again):
+        assert torch.equal(a, u["llr"])

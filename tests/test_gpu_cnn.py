@@ -439,3 +439,34 @@ def test_trained_denoiser_beats_plain_estimate():
             f"gated {c:7.2f} dB (gain {a - c:+.2f} dB)")
     assert gains[0.0] >= 3.0 and gains[10.0] >= 2.0
     assert gains[30.0] >= -0.1
+
+
+def test_training_resumes_from_a_checkpoint_bit_for_bit(tmp_path):
+    # 24 Adam steps uninterrupted against 10 steps, a checkpoint, and a new call resuming from
+    # it: parameters, Adam moments and losses equal bit for bit (the training kernels are
+    # deterministic and the checkpoint restores the minibatch stream).
+    from paper_2510_07843_amd import denoise
+    base = synth.SlotShape(20, 14, 8, 8, 6, 8, 2, (2,), 1)
+    data = synth.make_dmrs_batch(base, 12, seed=51, workers=8)
+    sh = data["shape"]
+    args = (ls_estimate(data), torch.from_numpy(data["h"]).cuda(),
+            torch.from_numpy(data["noise_var"]).cuda(), sh.n_slots, 1, sh.n_pilot,
+            sh.n_rx * sh.n_layers)
+    kw = dict(steps=24, batch=3, lr=3e-3, seed=52)
+    full = denoise.train(*args, **kw, checkpoint=str(tmp_path / "full.ck"))
+    part = str(tmp_path / "part.ck")
+    denoise.train(*args, **kw, checkpoint=part, checkpoint_every=5, stop_after=10)
+    ck = denoise.load_checkpoint(part)
+    assert ck["step"] == 10
+    rest = denoise.train(*args, **kw, resume=part, checkpoint=str(tmp_path / "rest.ck"))
+    torch.cuda.synchronize()
+    assert torch.equal(full["params"], rest["params"])
+    assert full["losses"] == rest["losses"]
+    a, b = (denoise.load_checkpoint(str(tmp_path / f)) for f in ("full.ck", "rest.ck"))
+    assert torch.equal(a["m"], b["m"]) and torch.equal(a["v"], b["v"]) and a["step"] == 24
+    # the stored network refines exactly as the trained one does
+    h = ls_estimate(data)
+    r1 = ranphy.cnn_denoise(sh, full["params"], h)
+    r2 = ranphy.cnn_denoise(sh, a["params"], h)
+    torch.cuda.synchronize()
+    assert torch.equal(r1, r2)
