@@ -355,6 +355,34 @@ def bfp_upload(torch, ranphy, shape, rx_dev, ms_step, re, fused_step=None):
     return out
 
 
+def held_out_curve(torch, synth, denoise, shape, ls, steps, cols, nimg, seed, points=12):
+    """The training objective on 14 held-out DMRS slots (two per SNR point 0, 5, .., 30 dB;
+    delay spread and Doppler drawn as for training, realisations of their own) at the
+    initial parameters and every steps / points steps, kept on the device until the end.
+    Returns the on_step hook for the trainer and a function that reads out the report."""
+    dev = torch.device("cuda:0")
+    grid = (0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0)
+    ho = synth.make_dmrs_batch(shape, 2 * len(grid), seed=44, snr_db=grid,
+                               workers=min(16, os.cpu_count() or 1))
+    n = 2 * len(grid)
+    he, ht = ls(ho), torch.from_numpy(ho["h"]).to(dev)
+    hv = torch.from_numpy(ho["noise_var"]).to(dev)
+    every = max(1, steps // points)
+    pts = [(0, denoise.validation_loss(denoise.init_params(seed, dev), he, ht, hv, n, 1, cols,
+                                       nimg))]
+    plain = denoise.validation_loss(None, he, ht, hv, n, 1, cols, nimg)
+
+    def on_step(step, p):
+        if step % every == 0 or step == steps:
+            pts.append((step, denoise.validation_loss(p, he, ht, hv, n, 1, cols, nimg)))
+
+    def report():
+        return {"slots": n, "snr_db": list(grid), "per_snr_point": 2,
+                "plain_estimate": round(float(plain.item()), 5),
+                "steps": [k for k, _ in pts], "loss": [round(float(l.item()), 5) for _, l in pts]}
+    return {"on_step": on_step, "report": report}
+
+
 def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96):
     """Train the pilot-estimate refinement on the GPU for the workload's DMRS grid (delay
     spread 30..300 ns, Doppler 0..500 Hz, SNR 0..30 dB) and choose its noise-variance gate by
@@ -378,9 +406,10 @@ def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96
         return ranphy.chest_ls(b["shape"], torch.from_numpy(b["rx"]).to(dev).reshape(-1),
                                torch.from_numpy(b["pilots"]).to(dev).reshape(-1))
 
+    curve = held_out_curve(torch, synth, denoise, shape, ls, steps, cols, nimg, seed=43)
     res = denoise.train(ls(tr), torch.from_numpy(tr["h"]).to(dev),
                         torch.from_numpy(tr["noise_var"]).to(dev), n_train, 1, cols, nimg,
-                        steps=steps, batch=batch, seed=43)
+                        steps=steps, batch=batch, seed=43, on_step=curve["on_step"])
     nmse = denoise.choose_gate(res["params"], ls(va), torch.from_numpy(va["h"]).to(dev),
                                torch.from_numpy(va["noise_var"]).to(dev), va["snr_db"], 1, cols,
                                nimg)
@@ -393,10 +422,86 @@ def train_refinement(torch, ranphy, synth, shape, steps=600, batch=2, n_train=96
                                     vs["snr_db"])
     report = {"train_slots": n_train, "images_per_slot": nimg, "steps": steps,
               "images_per_step": res["images_per_step"], "train_seconds": round(res["seconds"], 2),
-              "data_seconds": round(t_gen, 1), "loss_first_last": [res["losses"][0], res["losses"][-1]],
+              "data_seconds": round(t_gen, 1), "validation_loss": curve["report"](),
               "refine_up_to_snr_db": gate["max_snr_db"], "validation_sinr": gate["sinr"],
               "validation_nmse_at_pilots": nmse["nmse"]}
     return res["params"], gate["min_noise_var"], report
+
+
+def train_study(args, torch, ranphy, synth):
+    """The learned refinement trained with one optimisation budget (steps x batch slots) on
+    training sets of several sizes, nested (each set is a prefix of the next, slots drawn
+    as for the benchmark's training: delay spread 30..300 ns, Doppler 0..500 Hz, SNR
+    0..30 dB).  Per size: the held-out loss curve, the post-equalisation SINR of the FP32
+    detector with the plain and the (ungated) refined estimate per SNR point on full
+    validation slots of the 64 x 16 workload, the gate that SINR selects, and the NMSE at
+    the pilots at the largest delay spread.  Prints one JSON line."""
+    from paper_2510_07843_amd import denoise
+    dev = torch.device("cuda:0")
+    shape = synth.CONFIGS["m"]["shape"]
+    workers = min(16, os.cpu_count() or 1)
+    budgets = sorted(int(b) for b in args.train_study.split(","))
+    steps, batch, piece = args.study_steps, 2, 1024
+    ts = synth.dmrs_shape(shape, 1)
+    cols, nimg = ts.n_pilot, ts.n_rx * ts.n_layers
+    per = cols * nimg  # complex entries per slot
+
+    def ls(b):
+        return ranphy.chest_ls(b["shape"], torch.from_numpy(b["rx"]).to(dev).reshape(-1),
+                               torch.from_numpy(b["pilots"]).to(dev).reshape(-1))
+
+    def log(msg):
+        print(f"[train-study] {msg}", file=sys.stderr, flush=True)
+
+    top = budgets[-1]
+    he = torch.empty((top, per), dtype=torch.complex64, device=dev)
+    ht = torch.empty_like(he)
+    hv = torch.empty(top, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    for c in range(0, top, piece):
+        k = min(piece, top - c)
+        b = synth.make_dmrs_batch(shape, k, seed=41 if c == 0 else 41000 + c // piece,
+                                  workers=workers)
+        he[c:c + k] = ls(b).reshape(k, per)
+        ht[c:c + k] = torch.from_numpy(b["h"].reshape(k, per)).to(dev)
+        hv[c:c + k] = torch.from_numpy(b["noise_var"]).to(dev)
+        del b
+        log(f"training slots {c + k}/{top} generated ({time.perf_counter() - t0:.0f} s)")
+    t_gen = time.perf_counter() - t0
+    grid = (0.0, 5.0, 10.0, 15.0, 20.0, 25.0, 30.0)
+    va = synth.make_dmrs_batch(shape, 2 * len(grid), seed=42, snr_db=grid,
+                               tau_rms=synth.DMRS_RANGES["tau_rms"][1], workers=workers)
+    vs = synth.make_batch("m", n_slots=2 * len(synth.CONFIGS["m"]["snr_db"]), first_slot=1,
+                          workers=workers)
+    va_h, va_t = ls(va), torch.from_numpy(va["h"]).to(dev)
+    va_v = torch.from_numpy(va["noise_var"]).to(dev)
+    vs_rx = torch.from_numpy(vs["rx"]).to(dev).reshape(-1)
+    vs_p = torch.from_numpy(vs["pilots"]).to(dev).reshape(-1)
+    vs_v = torch.from_numpy(vs["noise_var"]).to(dev)
+    rows = []
+    for n in budgets:
+        curve = held_out_curve(torch, synth, denoise, shape, ls, steps, cols, nimg, seed=43,
+                               points=16)
+        res = denoise.train_stream([(he[:n], ht[:n], hv[:n], n)], 1, 1, cols, nimg,
+                                   steps=steps, batch=batch, seed=43, on_step=curve["on_step"])
+        gate = denoise.choose_gate_sinr(res["params"], vs["shape"], vs_rx, vs_p, vs_v, vs["x"],
+                                        vs["snr_db"])
+        nmse = denoise.choose_gate(res["params"], va_h, va_t, va_v, va["snr_db"], 1, cols, nimg)
+        rows.append({"train_slots": n, "passes": round(steps * batch / n, 2),
+                     "train_seconds": round(res["seconds"], 2),
+                     "validation_loss": curve["report"](),
+                     "train_loss_last100_steps": round(float(np.mean(res["losses"][-10:])), 5),
+                     "refine_up_to_snr_db": gate["max_snr_db"], "sinr": gate["sinr"],
+                     "nmse_at_pilots_tau300ns": nmse["nmse"]})
+        g = {r["snr_db"]: r["gain_db"] for r in gate["sinr"]}
+        log(f"{n} slots: SINR gain {g.get(0.0)} dB at 0 dB, {g.get(10.0)} dB at 10 dB, "
+            f"held-out loss {rows[-1]['validation_loss']['loss'][-1]}")
+    print(json.dumps({"study": "learned estimate refinement vs training-set size",
+                      "steps": steps, "batch_slots": batch, "lr": 2e-3,
+                      "images_per_slot": nimg, "data_seconds": round(t_gen, 1),
+                      "validation_slots": {"held_out_loss": 14, "sinr_full_slots": len(vs["snr_db"]),
+                                           "nmse": len(va["snr_db"])},
+                      "budgets": rows}), flush=True)
 
 
 def learned_quality(torch, ranphy, synth, params, min_nv):
@@ -630,6 +735,11 @@ def main():
                     help="skip training and timing the learned estimate refinement")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP16/BF16 detector runs and the SINR comparison")
+    ap.add_argument("--train-study", default=None, metavar="SLOTS,SLOTS,..",
+                    help="only train the learned refinement on training sets of these sizes "
+                         "(one optimisation budget) and report held-out loss and SINR gain")
+    ap.add_argument("--study-steps", type=int, default=4096,
+                    help="--train-study: Adam steps of two slots each per training set")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter reference)")
     args = ap.parse_args()
@@ -652,6 +762,9 @@ def main():
     import paper_2510_07843_amd as ranphy
     import synth
 
+    if args.train_study:
+        train_study(args, torch, ranphy, synth)
+        return
     if args.workload == "batch":
         bench_batch(args, torch, ranphy, synth)
         return

@@ -12,7 +12,7 @@ import json
 import math
 import os
 import time
-from typing import Dict, Optional, Sequence
+from typing import Dict, Iterable, Optional, Sequence
 
 import numpy as np
 import torch
@@ -132,6 +132,18 @@ def _as_groups(h: torch.Tensor, n_slots: int) -> torch.Tensor:
     return torch.view_as_real(h.reshape(-1)).reshape(n_slots, -1)
 
 
+def _update(p, m, v, x_all, t_all, noise_var, idx, rows, cols, n_img, ws, step, steps, lr):
+    """One Adam step on the slots idx of the grouped data; the cosine-decayed learning rate
+    (floored at 1 % of lr) at step of steps.  Returns the minibatch loss (a device tensor)."""
+    xb = x_all.index_select(0, idx).reshape(-1).contiguous()
+    tb = t_all.index_select(0, idx).reshape(-1).contiguous()
+    nb = noise_var.index_select(0, idx).contiguous()
+    loss, grad = cnn_grad(p, xb, tb, rows, cols, n_img, idx.numel(), workspace=ws, noise_var=nb)
+    rate = lr * max(0.5 * (1.0 + math.cos(math.pi * step / steps)), 0.01)
+    cnn_adam(p, grad, m, v, step, rate)
+    return loss
+
+
 def train(h_est: torch.Tensor, h_true: torch.Tensor, noise_var: torch.Tensor, n_slots: int,
           rows: int, cols: int, n_img: int, steps: int = 300, batch: int = 4, lr: float = 2e-3,
           seed: int = 0, params: Optional[torch.Tensor] = None, resume: Optional[str] = None,
@@ -177,12 +189,8 @@ def train(h_est: torch.Tensor, h_true: torch.Tensor, noise_var: torch.Tensor, n_
     t0 = time.perf_counter()
     for step in range(first, last + 1):
         idx = torch.from_numpy(rng.choice(n_slots, batch, replace=False)).to(dev)
-        xb = x_all.index_select(0, idx).reshape(-1).contiguous()
-        tb = t_all.index_select(0, idx).reshape(-1).contiguous()
-        nb = noise_var.index_select(0, idx).contiguous()
-        loss, grad = cnn_grad(p, xb, tb, rows, cols, n_img, batch, workspace=ws, noise_var=nb)
-        rate = lr * max(0.5 * (1.0 + math.cos(math.pi * step / steps)), 0.01)
-        cnn_adam(p, grad, m, v, step, rate)
+        loss = _update(p, m, v, x_all, t_all, noise_var, idx, rows, cols, n_img, ws, step,
+                       steps, lr)
         if step % 10 == 0:
             losses.append(loss)
         if on_step is not None:
@@ -193,6 +201,71 @@ def train(h_est: torch.Tensor, h_true: torch.Tensor, noise_var: torch.Tensor, n_
     dt = time.perf_counter() - t0
     return dict(params=p, losses=[float(l.item()) for l in losses], seconds=dt, steps=steps,
                 batch=batch, images_per_step=batch * n_img, last_step=last)
+
+
+def train_stream(chunks: Iterable, n_chunks: int, rows: int, cols: int, n_img: int,
+                 steps: int = 300, batch: int = 4, lr: float = 2e-3, seed: int = 0,
+                 params: Optional[torch.Tensor] = None, on_step=None) -> Dict:
+    """Adam as in train() over a training set held a chunk at a time (for sets larger than
+    memory).  chunks yields n_chunks tuples (h_est, h_true, noise_var, n_slots); the steps
+    are split evenly over the chunks (the first ones take the remainder) and, within a
+    chunk, the minibatches walk seeded permutations of its slots, so that a chunk given
+    n_slots / batch steps is passed over exactly once.  The learning rate decays over all
+    steps as in train().  Returns what train() returns, plus the slots seen."""
+    if n_chunks < 1 or steps < n_chunks:
+        raise ValueError("train_stream: need at least one chunk and one step per chunk")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([0xC24, seed])))
+    it = iter(chunks)
+    p = m = v = ws = None
+    losses, step, seen, dt = [], 0, 0, 0.0
+    for c in range(n_chunks):
+        h_est, h_true, noise_var, n_slots = next(it)
+        if n_slots < batch:
+            raise ValueError("train_stream: a chunk holds fewer slots than a minibatch")
+        dev = h_est.device
+        if p is None:
+            p = init_params(seed, dev) if params is None else params
+            m, v = torch.zeros_like(p), torch.zeros_like(p)
+            ws = torch.empty(cnn_workspace_bytes(rows, cols, n_img, batch, True),
+                             dtype=torch.uint8, device=dev)
+        x_all, t_all = _as_groups(h_est, n_slots), _as_groups(h_true, n_slots)
+        k = steps // n_chunks + (1 if c < steps % n_chunks else 0)
+        order = np.concatenate([rng.permutation(n_slots)
+                                for _ in range(-(-k * batch // n_slots))])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k):
+            step += 1
+            idx = torch.from_numpy(order[i * batch:(i + 1) * batch]).to(dev)
+            loss = _update(p, m, v, x_all, t_all, noise_var, idx, rows, cols, n_img, ws, step,
+                           steps, lr)
+            if step % 10 == 0:
+                losses.append(loss)
+            if on_step is not None:
+                on_step(step, p)
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+        seen += min(n_slots, k * batch)
+        del x_all, t_all, h_est, h_true, noise_var
+    return dict(params=p, losses=[float(l.item()) for l in losses], seconds=dt, steps=steps,
+                batch=batch, images_per_step=batch * n_img, last_step=step, slots_seen=seen)
+
+
+def validation_loss(params: Optional[torch.Tensor], h_est: torch.Tensor, h_true: torch.Tensor,
+                    noise_var: torch.Tensor, n_slots: int, rows: int, cols: int,
+                    n_img: int) -> torch.Tensor:
+    """The training objective on held-out slots: the mean squared error per real component
+    between the refined estimate and the truth, each slot's divided by its noise variance
+    (the loss of ranphy_cnn_grad); with params None that of the plain estimate.  A device
+    scalar, so that a curve of it costs no synchronisation."""
+    x, t = _as_groups(h_est, n_slots), _as_groups(h_true, n_slots)
+    if params is None:
+        out = x
+    else:
+        out = cnn_forward(params, x.reshape(-1).contiguous(), rows, cols, n_img, n_slots,
+                          noise_var=noise_var).reshape(n_slots, -1)
+    per_slot = ((out - t) ** 2).sum(dim=1) / noise_var
+    return per_slot.sum() / t.numel()
 
 
 def nmse_db(est: torch.Tensor, true: torch.Tensor) -> float:

@@ -388,7 +388,9 @@ def make_dmrs_slot(shape: SlotShape, rng: np.random.Generator, scs_hz: float, ta
     g = g.sum(axis=3) * np.sqrt(powers / n_sinusoids)[:, None, None, None]  # [tap][rx][port][t]
     k = (np.arange(NL)[None, :] % C) + C * np.arange(J)[:, None]  # [j][port]
     steer = np.exp(-2j * np.pi * scs_hz * k[..., None] * delays)   # [j][port][tap]
-    Ht = np.einsum("jpn,nrpt->tjrp", steer, g)                     # [t][j][rx][port]
+    # [t][j][rx][port]: per port, [j][tap] @ [tap][rx t] (a BLAS product per port)
+    Ht = np.matmul(steer.transpose(1, 0, 2), g.transpose(2, 0, 1, 3).reshape(NL, nt, NR * T))
+    Ht = Ht.reshape(NL, J, NR, T).transpose(3, 1, 2, 0)
     inband = (k < nsc)[None, :, None, :]
     Ht = np.where(inband, Ht, 0)
     y = np.zeros((shape.n_symb, nsc, NR), np.complex128)
@@ -435,7 +437,11 @@ def make_dmrs_batch(shape: SlotShape, n_slots: int, seed: int, scs_hz: float = 3
 
     if workers > 1:
         import concurrent.futures as cf
-        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        from threadpoolctl import threadpool_limits
+        # one BLAS thread per worker: the per-port products are small, and BLAS's own
+        # threads on top of the workers' oversubscribe the cores
+        with threadpool_limits(limits=1, user_api="blas"), \
+                cf.ThreadPoolExecutor(max_workers=workers) as ex:
             list(ex.map(one, range(n_slots)))
     else:
         for i in range(n_slots):

@@ -470,3 +470,40 @@ def test_training_resumes_from_a_checkpoint_bit_for_bit(tmp_path):
     r2 = ranphy.cnn_denoise(sh, a["params"], h)
     torch.cuda.synchronize()
     assert torch.equal(r1, r2)
+
+
+def test_streamed_training_and_held_out_loss():
+    # validation_loss is the objective ranphy_cnn_grad reports (the same slots through both),
+    # and for the plain estimate the noise-normalised MSE written out in NumPy; train_stream
+    # over two chunks takes every step, passes over each chunk, and lowers the objective on
+    # the data it saw.
+    from paper_2510_07843_amd import denoise
+    base = synth.SlotShape(20, 14, 8, 8, 6, 8, 2, (2,), 1)
+    data = synth.make_dmrs_batch(base, 12, seed=61, workers=8)
+    sh = data["shape"]
+    cols, nimg = sh.n_pilot, sh.n_rx * sh.n_layers
+    he = ls_estimate(data).reshape(12, -1)
+    ht = torch.from_numpy(data["h"]).cuda().reshape(12, -1)
+    hv = torch.from_numpy(data["noise_var"]).cuda()
+    p0 = denoise.init_params(62, "cuda")
+    x = torch.view_as_real(he).reshape(-1).contiguous()
+    t = torch.view_as_real(ht).reshape(-1).contiguous()
+    lg, _ = ranphy.cnn_grad(p0, x, t, 1, cols, nimg, 12, noise_var=hv)
+    lv = denoise.validation_loss(p0, he, ht, hv, 12, 1, cols, nimg)
+    plain = denoise.validation_loss(None, he, ht, hv, 12, 1, cols, nimg)
+    torch.cuda.synchronize()
+    e = he.cpu().numpy() - data["h"].reshape(12, -1)
+    want = np.sum(np.abs(e) ** 2 / data["noise_var"][:, None].astype(np.float64)) / (2 * e.size)
+    say(f"held-out objective {lv.item():.6f} (cnn_grad {lg.item():.6f}), plain {plain.item():.6f}")
+    assert abs(lv.item() - lg.item()) <= 1e-3 * lg.item()
+    assert abs(plain.item() - want) <= 1e-5 * want
+    chunks = [(he[:6], ht[:6], hv[:6], 6), (he[6:], ht[6:], hv[6:], 6)]
+    res = denoise.train_stream(iter(chunks), 2, 1, cols, nimg, steps=40, batch=2, lr=3e-3,
+                               seed=62)
+    after = denoise.validation_loss(res["params"], he, ht, hv, 12, 1, cols, nimg)
+    torch.cuda.synchronize()
+    say(f"streamed: {res['last_step']} steps, {res['slots_seen']} slots seen, objective "
+        f"{lv.item():.6f} -> {after.item():.6f}")
+    assert res["last_step"] == 40 and res["slots_seen"] == 12 and len(res["losses"]) == 4
+    assert torch.isfinite(res["params"]).all()
+    assert after.item() < lv.item()
