@@ -57,18 +57,24 @@ struct TileCap<8, 3> {
   static constexpr bool one_occ = false;
   // pilot estimates per thread whose loads are in flight together
   static constexpr int stage_batch = 4;
+  // LLRs per element written as one record by lane groups (0: lane by lane).  The
+  // multi-UE form keeps lane-by-lane stores: the record exchange's registers cost it more
+  // (spills) than the scattered stores do (measured).
+  static constexpr int store_floats = 0;
 };
 template <>
 struct TileCap<4, 4> {  // two-occasion tiles of 16 x 4 fit 21 subcarriers
   static constexpr int rows = 3776, fac = 1024, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
   static constexpr bool one_occ = false;
   static constexpr int stage_batch = 4;
+  static constexpr int store_floats = 32;  // whole 128-byte records of 4 layers x 256QAM
 };
 template <>
 struct TileCap<4, 5> {  // one-occasion tiles only
   static constexpr int rows = 2944, fac = 640, fnp = 10, aux = 2 * 4 + 1, fsc = kBatchFactSc;
   static constexpr bool one_occ = true;
   static constexpr int stage_batch = 1;  // within the 5-block register budget
+  static constexpr int store_floats = 0;   // likewise (measured on the paper's 2x2 and 4x4)
 };
 
 __host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk, int cap_rows,

@@ -90,23 +90,158 @@ __device__ __forceinline__ void cmsb_c(float2& acc, float2 a, float2 b) {
   acc.y = fmaf(a.y, b.x, acc.y);
 }
 
-// LLRs of one layer of one RE (compile-time Qm: the values stay in registers).
-template <int QM>
-__device__ __forceinline__ void demap_store(float* __restrict__ dst, float2 xo, float vo) {
-  float out[QM];
-  llr_one<QM>(xo, vo, out);
+// One exchange stage of the in-group chunk transpose of store_records, for the member-index
+// bit S that lane bit LB carries (LB = 2 or 3: the partner lies 4 or 8 lanes away in the same
+// DPP row, and the DPP bank mask picks the lanes that take the moved value, so the stage is
+// one DPP move per value).  Members with the bit clear take the partner's chunk a into slot
+// a | S; members with it set take the partner's chunk a | S into slot a.
+template <int P, int S, int LB>
+__device__ __forceinline__ void xpose_stage_bank(int (&c)[P][4]) {
+  constexpr int up = 0x100 | (1 << LB), down = 0x110 | (1 << LB);  // row_shl / row_shr
+  constexpr int lo_banks = LB == 2 ? 0x5 : 0x3, hi_banks = LB == 2 ? 0xA : 0xC;
 #pragma unroll
-  for (int b = 0; b < QM; b += 2)
-    *reinterpret_cast<float2*>(dst + b) = make_float2(out[b], out[b + 1]);
+  for (int a = 0; a < P; ++a) {
+    if (a & S) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int hi = __builtin_amdgcn_update_dpp(c[a | S][q], c[a][q], up, 0xF, lo_banks, false);
+      const int lo = __builtin_amdgcn_update_dpp(c[a][q], c[a | S][q], down, 0xF, hi_banks, false);
+      c[a | S][q] = hi;
+      c[a][q] = lo;
+    }
+  }
+}
+
+// The same stage for member bit S carried by lane bit 0 (partner: the neighbouring lane of
+// the quad), where lanes are told apart by a select.
+template <int P, int S>
+__device__ __forceinline__ void xpose_stage_quad(int (&c)[P][4], bool odd) {
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    if (a & S) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int from_a = __builtin_amdgcn_mov_dpp(c[a][q], 0xB1, 0xF, 0xF, false);      // lane ^ 1
+      const int from_as = __builtin_amdgcn_mov_dpp(c[a | S][q], 0xB1, 0xF, 0xF, false);
+      const int hi = odd ? c[a | S][q] : from_a;
+      const int lo = odd ? from_as : c[a][q];
+      c[a | S][q] = hi;
+      c[a][q] = lo;
+    }
+  }
+}
+
+// Groups of P = 2, 4 or 8 lanes exchanging 16-byte chunks (store_records).  A
+// lane's member index within its group takes bit 0 from lane bit 2, bit 1 from lane bit 3
+// and bit 2 from lane bit 0; ml(i) is the lane of member i.
+template <int P>
+__device__ __forceinline__ int group_member(int lane) {
+  return ((lane >> 2) & 1) | (P >= 4 ? ((lane >> 3) & 1) << 1 : 0) |
+         (P == 8 ? (lane & 1) << 2 : 0);
+}
+template <int P>
+__device__ __forceinline__ int group_lane(int lane, int i) {
+  return (lane & ~(P == 8 ? 0xD : (P == 4 ? 0xC : 0x4))) | ((i & 1) << 2) |
+         (((i >> 1) & 1) << 3) | ((i >> 2) & 1);
+}
+// Transpose within each group: afterwards member m's slot i holds what member i's slot m held.
+template <int P>
+__device__ __forceinline__ void group_transpose(int (&c)[P][4], int lane) {
+  xpose_stage_bank<P, 1, 2>(c);
+  if constexpr (P >= 4) xpose_stage_bank<P, 2, 3>(c);
+  if constexpr (P == 8) xpose_stage_quad<P, 4>(c, lane & 1);
+}
+
+// Writes the LLR records of the resource elements the lanes of a wave hold (R floats per
+// lane, R a multiple of 4, 8..32) so that every store instruction writes whole records:
+// stored lane by lane, one 16-byte piece of a record per instruction, each instruction would
+// touch a different cache line per lane, and the address and data path handles a line at a
+// time.  A record is split into P >= R / 4 chunks of 16 bytes, the chunks are transposed
+// within the lane groups (member m then holds chunk m of every member's record), and store i
+// writes member i's record, one chunk per lane.  off is the record's offset in floats from
+// base, negative where the lane holds no element.  Every lane of the wave must call this
+// (the exchanges read the other lanes).
+template <int R>
+__device__ __forceinline__ void store_records(float* __restrict__ base, int off,
+                                              const float (&out)[R]) {
+  constexpr int NC = R / 4;
+  constexpr int P = NC <= 2 ? 2 : (NC <= 4 ? 4 : 8);
+  const int lane = (int)(threadIdx.x & 63);
+  const int me = group_member<P>(lane);
+  int c[P][4];
+#pragma unroll
+  for (int i = 0; i < P; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[i][q] = i < NC ? __float_as_int(out[4 * i + q]) : 0;
+  group_transpose<P>(c, lane);
+  const bool wide = (reinterpret_cast<uintptr_t>(base) & 15) == 0;  // else 8-byte pieces
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int oi = __builtin_amdgcn_ds_bpermute(group_lane<P>(lane, i) << 2, off);
+    if (oi >= 0 && me < NC) {
+      float* dst = base + oi + 4 * me;
+      const float4 v = make_float4(__int_as_float(c[i][0]), __int_as_float(c[i][1]),
+                                   __int_as_float(c[i][2]), __int_as_float(c[i][3]));
+      if (wide) {
+        *reinterpret_cast<float4*>(dst) = v;
+      } else {
+        reinterpret_cast<float2*>(dst)[0] = make_float2(v.x, v.y);
+        reinterpret_cast<float2*>(dst)[1] = make_float2(v.z, v.w);
+      }
+    }
+  }
+}
+
+// Layers L0 .. NL - 1 of one element's LLRs into its record llr[off ..], NS layers at a time
+// (a slice of NS * QM floats held in registers at once): by store_records where a slice is a
+// whole number of 16-byte chunks (8..32 floats), else lane by lane; off < 0: the lane holds
+// no element (it still takes part in the exchanges).
+template <int NL, int QM, int NS, int L0, int MAXR>
+__device__ __forceinline__ void emit_slices(float* __restrict__ llr, int off,
+                                            const float2 (&xo)[NL], const float (&vo)[NL]) {
+  if constexpr (L0 < NL) {
+    constexpr int N = NS < NL - L0 ? NS : NL - L0;
+    constexpr int R = N * QM;
+    float out[R];
+#pragma unroll
+    for (int l = 0; l < N; ++l) llr_one<QM>(xo[L0 + l], vo[L0 + l], out + l * QM);
+    const int o = off >= 0 ? off + L0 * QM : -1;
+    if constexpr (R % 4 == 0 && R >= 8 && R <= 32 && R <= MAXR) {
+      store_records<R>(llr, o, out);
+    } else if (o >= 0) {
+#pragma unroll
+      for (int b = 0; b < R; b += 2)
+        *reinterpret_cast<float2*>(llr + o + b) = make_float2(out[b], out[b + 1]);
+    }
+    emit_slices<NL, QM, NS, L0 + N, MAXR>(llr, off, xo, vo);
+  }
+}
+
+// The element's LLRs for the launch's modulation (uniform over the launch), in slices of at
+// most MAXR floats (the register room of the kernel form; 64QAM slices hold an even number
+// of layers, so that they stay whole 16-byte chunks; MAXR below 8: lane by lane).  off: the element's record in floats
+// from llr (one slot's or UE's LLRs stay below 2^31), negative for none.
+template <int NL, int MAXR>
+__device__ __forceinline__ void emit_element(const Geom& g, float* __restrict__ llr, int off,
+                                             const float2 (&xo)[NL], const float (&vo)[NL]) {
+  constexpr int NS2 = MAXR / 2 < 1 ? 1 : MAXR / 2, NS4 = MAXR / 4 < 1 ? 1 : MAXR / 4;
+  constexpr int NS8 = MAXR / 8 < 1 ? 1 : MAXR / 8;
+  constexpr int NS6 = MAXR / 12 * 2 < 1 ? 1 : MAXR / 12 * 2;
+  switch (g.qm) {
+    case 2: emit_slices<NL, 2, NS2, 0, MAXR>(llr, off, xo, vo); break;
+    case 4: emit_slices<NL, 4, NS4, 0, MAXR>(llr, off, xo, vo); break;
+    case 6: emit_slices<NL, 6, NS6, 0, MAXR>(llr, off, xo, vo); break;
+    default: emit_slices<NL, 8, NS8, 0, MAXR>(llr, off, xo, vo); break;
+  }
 }
 
 // Resource element (data symbol d, subcarrier k) from its Gram G = H^H H (lower triangle) and
 // matched filter z = H^H y: G + s2 I = L L^H (Cholesky, Sec. IV, Fig. 4), forward and backward
 // substitution, d_l = || L^-1 e_l ||^2, unbiasing, max-log LLRs into llr[d][k][layer][qm].
-template <int NL>
+template <int NL, int MAXR>
 __device__ __forceinline__ void solve_emit(const Geom& g, float* __restrict__ llr, int d, int k,
-                                           float2 (&G)[NL * (NL + 1) / 2], float2 (&z)[NL],
-                                           float s2) {
+                                           bool valid, float2 (&G)[NL * (NL + 1) / 2],
+                                           float2 (&z)[NL], float s2) {
   float gd[NL];
 #pragma unroll
   for (int i = 0; i < NL; ++i) {
@@ -157,9 +292,10 @@ __device__ __forceinline__ void solve_emit(const Geom& g, float* __restrict__ ll
     }
     xh[i] = make_float2(acc.x * linv[i], acc.y * linv[i]);
   }
-  float* __restrict__ dst = llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+  float2 xo[NL];
+  float vo[NL];
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2, unbias, demap
+  for (int l = 0; l < NL; ++l) {  // d_l = || L^-1 e_l ||^2, unbias
     float2 uu[NL];
     uu[l] = make_float2(linv[l], 0.f);
     float acc2 = linv[l] * linv[l];
@@ -175,26 +311,25 @@ __device__ __forceinline__ void solve_emit(const Geom& g, float* __restrict__ ll
     }
     const float sd = s2 * acc2;
     const float im = __builtin_amdgcn_rcpf(1.f - sd);
-    const float2 xo = ok ? make_float2(xh[l].x * im, xh[l].y * im)
-                         : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-    const float vo = ok ? sd * im : __builtin_inff();
-    switch (g.qm) {  // uniform over the item
-      case 2: demap_store<2>(dst + l * 2, xo, vo); break;
-      case 4: demap_store<4>(dst + l * 4, xo, vo); break;
-      case 6: demap_store<6>(dst + l * 6, xo, vo); break;
-      default: demap_store<8>(dst + l * 8, xo, vo); break;
-    }
+    xo[l] = ok ? make_float2(xh[l].x * im, xh[l].y * im)
+               : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    vo[l] = ok ? sd * im : __builtin_inff();
   }
+  emit_element<NL, MAXR>(g, llr, valid ? (d * g.n_sc + k) * NL * g.qm : -1, xo, vo);
 }
 
-template <int NL, int RXF>
+template <int NL, int RXF, int MAXR>
 __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int k0, int nk,
                                             int jlo, int nj,
                             const float2* __restrict__ lds, const SymTab& tab) {
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
   const FastDiv by_nk(nk);
-  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
+  const int total = nk * ND, lane = (int)(threadIdx.x & 63);
+  // wave-uniform trips: every lane takes part in the record stores of solve_emit
+  for (int e0 = (int)threadIdx.x - lane; e0 < total; e0 += blockDim.x) {
+    const bool valid = e0 + lane < total;
+    const int e = valid ? e0 + lane : total - 1;
     const int d = by_nk(e);
     const int k = k0 + (e - d * nk);
     const int s = tab.dsym[d];
@@ -238,7 +373,7 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
         for (int j = 0; j <= i; ++j) cmac_c(G[tri(i, j)], hr[i], hr[j]);
       }
     }
-    solve_emit<NL>(g, u.llr, d, k, G, z, s2);
+    solve_emit<NL, MAXR>(g, u.llr, d, k, valid, G, z, s2);
   }
 }
 
@@ -250,7 +385,7 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
 // once; float4 (H0, D) per antenna and layer in pair[]) and A, S, C (in gram[]); each
 // resource element then blends its Gram, forms z = (H0 + t D)^H y from the staged pairs and
 // finishes as the other paths do.
-template <int NL, int RXF>
+template <int NL, int RXF, int MAXR>
 __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g, int k0, int nk,
                                                  int jlo, int nj,
                                  const float2* __restrict__ rows, float4* __restrict__ pair,
@@ -258,65 +393,97 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
   constexpr int NP = NL * (NL + 1) / 2;
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const int PS = batch_pair_stride(NR, NL), GS = batch_gram_stride(NL);
-  const FastDiv by_nr(NR);
-  for (int f = threadIdx.x; f < nk * NR; f += blockDim.x) {  // (subcarrier, antenna)
-    const int kk = by_nr(f);
-    const int r = f - kk * NR;
-    const int k = k0 + kk;
+  // channel pairs: items (subcarrier, layer, group of 8 antennas), so that a layer's
+  // interpolation rule is found once per 8 antennas
+  const int nch = (NR + 7) >> 3;
+  const FastDiv by_nch(nch);
+  for (int f = threadIdx.x; f < nk * NL * nch; f += blockDim.x) {
+    const int kp = by_nch(f);
+    const int c = f - kp * nch;
+    const int kk = kp / NL;
+    const int p = kp - kk * NL;
+    int j0, j1;
+    float a;
+    freq_rule(g, p, k0 + kk, j0, j1, a);
+    const float2* b0 = rows + (j0 - jlo) * RS + p;
+    const float2* b1 = rows + (j1 - jlo) * RS + p;
+    const float2* c0 = rows + (nj + j0 - jlo) * RS + p;
+    const float2* c1 = rows + (nj + j1 - jlo) * RS + p;
+    float4* dst = pair + kk * PS + p;
 #pragma unroll
-    for (int p = 0; p < NL; ++p) {
-      int j0, j1;
-      float a;
-      freq_rule(g, p, k, j0, j1, a);
-      const float2* b = rows + r * NL + p;
-      const float2 v0 = b[(j0 - jlo) * RS], v1 = b[(j1 - jlo) * RS];
-      const float2 u0 = b[(nj + j0 - jlo) * RS], u1 = b[(nj + j1 - jlo) * RS];
-      const float2 h0 = make_float2(v0.x + a * (v1.x - v0.x), v0.y + a * (v1.y - v0.y));
-      const float2 h1 = make_float2(u0.x + a * (u1.x - u0.x), u0.y + a * (u1.y - u0.y));
-      pair[kk * PS + r * NL + p] = make_float4(h0.x, h0.y, h1.x - h0.x, h1.y - h0.y);
+    for (int rr = 0; rr < 8; ++rr) {
+      const int r = 8 * c + rr;
+      if (r < NR) {
+        const float2 v0 = b0[r * NL], v1 = b1[r * NL], u0 = c0[r * NL], u1 = c1[r * NL];
+        const float2 h0 = make_float2(v0.x + a * (v1.x - v0.x), v0.y + a * (v1.y - v0.y));
+        const float2 h1 = make_float2(u0.x + a * (u1.x - u0.x), u0.y + a * (u1.y - u0.y));
+        dst[r * NL] = make_float4(h0.x, h0.y, h1.x - h0.x, h1.y - h0.y);
+      }
     }
   }
   __syncthreads();
-  for (int f = threadIdx.x; f < nk * NP; f += blockDim.x) {  // (subcarrier, Gram entry)
-    const int kk = f / NP;
-    const int e = f - kk * NP;
-    int i = 0;
-    while ((i + 1) * (i + 2) / 2 <= e) ++i;
-    const int j = e - i * (i + 1) / 2;
-    float2 A = make_float2(0.f, 0.f), S = A, C = A;
+  // Gram pieces: items (subcarrier, entry), the strictly lower entries first and then the
+  // diagonal ones, so that most waves hold one kind; a diagonal entry is real (its imaginary
+  // part is not used) and S_ii = 2 Re(h0_i^H h1_i), a third of the off-diagonal work
+  constexpr int NOFF = NP - NL, NOFF1 = NOFF > 0 ? NOFF : 1;
+  const int n_off = nk * NOFF;
+  for (int f = threadIdx.x; f < n_off + nk * NL; f += blockDim.x) {
+    const bool off = f < n_off;
+    const int kk = off ? f / NOFF1 : (f - n_off) / NL;
     const float4* q = pair + kk * PS;
-    for (int r = 0; r < NR; ++r) {
-      const float4 qi = q[r * NL + i], qj = q[r * NL + j];
-      const float2 h0i = make_float2(qi.x, qi.y), h0j = make_float2(qj.x, qj.y);
-      const float2 h1i = make_float2(qi.x + qi.z, qi.y + qi.w);
-      const float2 h1j = make_float2(qj.x + qj.z, qj.y + qj.w);
-      cmac_c(A, h0i, h0j);
-      cmac_c(C, h1i, h1j);
-      cmac_c(S, h0i, h1j);
-      cmac_c(S, h1i, h0j);
-    }
     float2* gg = gram + kk * GS;
-    gg[e] = A;
-    gg[NP + e] = S;
-    gg[2 * NP + e] = C;
+    if (off) {
+      const int m = f - kk * NOFF;
+      int i = 1;
+#pragma unroll
+      for (int cc = 2; cc < NL; ++cc) i += m >= cc * (cc - 1) / 2;
+      const int j = m - i * (i - 1) / 2;
+      float2 A = make_float2(0.f, 0.f), S = A, C = A;
+      for (int r = 0; r < NR; ++r) {
+        const float4 qi = q[r * NL + i], qj = q[r * NL + j];
+        const float2 h0i = make_float2(qi.x, qi.y), h0j = make_float2(qj.x, qj.y);
+        const float2 h1i = make_float2(qi.x + qi.z, qi.y + qi.w);
+        const float2 h1j = make_float2(qj.x + qj.z, qj.y + qj.w);
+        cmac_c(A, h0i, h0j);
+        cmac_c(C, h1i, h1j);
+        cmac_c(S, h0i, h1j);
+        cmac_c(S, h1i, h0j);
+      }
+      const int e = tri(i, j);
+      gg[e] = A;
+      gg[NP + e] = S;
+      gg[2 * NP + e] = C;
+    } else {
+      const int i = f - n_off - kk * NL;
+      float a = 0.f, sr = 0.f, cr = 0.f;
+      for (int r = 0; r < NR; ++r) {
+        const float4 qi = q[r * NL + i];
+        const float h1x = qi.x + qi.z, h1y = qi.y + qi.w;
+        a = fmaf(qi.y, qi.y, fmaf(qi.x, qi.x, a));
+        cr = fmaf(h1y, h1y, fmaf(h1x, h1x, cr));
+        sr = fmaf(qi.y, h1y, fmaf(qi.x, h1x, sr));
+      }
+      const int e = tri(i, i);
+      gg[e] = make_float2(a, 0.f);
+      gg[NP + e] = make_float2(2.f * sr, 0.f);
+      gg[2 * NP + e] = make_float2(cr, 0.f);
+    }
   }
   __syncthreads();
   const float s2 = *u.nv;
   const FastDiv by_nk(nk);
-  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {  // resource elements
+  const int total = nk * ND, lane = (int)(threadIdx.x & 63);
+  // resource elements, wave-uniform trips: every lane takes part in the record stores
+  for (int e0 = (int)threadIdx.x - lane; e0 < total; e0 += blockDim.x) {
+    const bool valid = e0 + lane < total;
+    const int e = valid ? e0 + lane : total - 1;
     const int d = by_nk(e);
     const int kk = e - d * nk;
     const int k = k0 + kk;
     const int o0 = tab.o0[d], o1 = tab.o1[d];
     const float t = o0 == o1 ? (float)o0 : tab.w[d];
     const float w0 = (1.f - t) * (1.f - t), w1 = t * (1.f - t), w2 = t * t;
-    const float2* gg = gram + kk * GS;
     float2 G[NP], z[NL];
-#pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      const float2 A = gg[i], S = gg[NP + i], C = gg[2 * NP + i];
-      G[i] = make_float2(w0 * A.x + w1 * S.x + w2 * C.x, w0 * A.y + w1 * S.y + w2 * C.y);
-    }
 #pragma unroll
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
     const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
@@ -331,7 +498,13 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
         cmac_c(z[p], h, y);
       }
     }
-    solve_emit<NL>(g, u.llr, d, k, G, z, s2);
+    const float2* gg = gram + kk * GS;  // blended after the matched filter: fewer live values
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const float2 A = gg[i], S = gg[NP + i], C = gg[2 * NP + i];
+      G[i] = make_float2(w0 * A.x + w1 * S.x + w2 * C.x, w0 * A.y + w1 * S.y + w2 * C.y);
+    }
+    solve_emit<NL, MAXR>(g, u.llr, d, k, valid, G, z, s2);
   }
 }
 
@@ -446,7 +619,11 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
   const int NR = g.n_rx, ND = g.n_dsym, RS = batch_row_stride(NR, NL);
   const float s2 = *u.nv;
   const FastDiv by_nk(nk);
-  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
+  const int total = nk * ND, lane = (int)(threadIdx.x & 63);
+  // wave-uniform trips: every lane takes part in the record stores
+  for (int e0 = (int)threadIdx.x - lane; e0 < total; e0 += blockDim.x) {
+    const bool valid = e0 + lane < total;
+    const int e = valid ? e0 + lane : total - 1;
     const int d = by_nk(e);
     const int kk = e - d * nk;
     const int k = k0 + kk;
@@ -492,21 +669,18 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
       }
       xh[i] = make_float2(acc.x * ax[i], acc.y * ax[i]);
     }
-    float* __restrict__ dst = u.llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+    float2 xo[NL];
+    float vo[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const float sd = s2 * ax[NL + l];
       const float im = 1.f / (1.f - sd);
-      const float2 xo = ok ? make_float2(xh[l].x * im, xh[l].y * im)
-                           : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-      const float vo = ok ? sd * im : __builtin_inff();
-      switch (g.qm) {
-        case 2: demap_store<2>(dst + l * 2, xo, vo); break;
-        case 4: demap_store<4>(dst + l * 4, xo, vo); break;
-        case 6: demap_store<6>(dst + l * 6, xo, vo); break;
-        default: demap_store<8>(dst + l * 8, xo, vo); break;
-      }
+      xo[l] = ok ? make_float2(xh[l].x * im, xh[l].y * im)
+                 : make_float2(__builtin_nanf(""), __builtin_nanf(""));
+      vo[l] = ok ? sd * im : __builtin_inff();
     }
+    emit_element<NL, CAP::store_floats>(g, u.llr, valid ? (d * g.n_sc + k) * NL * g.qm : -1, xo,
+                                        vo);
   }
 }
 
@@ -645,7 +819,11 @@ __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, i
   }
   __syncthreads();
   const FastDiv by_nk(nk);
-  for (int e = threadIdx.x; e < nk * ND; e += blockDim.x) {
+  const int total = nk * ND, lane = (int)(threadIdx.x & 63);
+  // wave-uniform trips: every lane takes part in the record stores
+  for (int e0 = (int)threadIdx.x - lane; e0 < total; e0 += blockDim.x) {
+    const bool valid = e0 + lane < total;
+    const int e = valid ? e0 + lane : total - 1;
     const int d = by_nk(e);
     const int kk = e - d * nk;
     const int k = k0 + kk;
@@ -668,19 +846,16 @@ __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, i
         x[l].y = fmaf(c.y, y.x, x[l].y);
       }
     }
-    float* __restrict__ dst = u.llr + (((int64_t)d * g.n_sc + k) * NL) * g.qm;
+    float2 xo[NL];
+    float vo[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
       const float sd = s2 * ax[NL + l];
-      const float vo = ok ? sd * __builtin_amdgcn_rcpf(1.f - sd) : __builtin_inff();
-      const float2 xo = ok ? x[l] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
-      switch (g.qm) {
-        case 2: demap_store<2>(dst + l * 2, xo, vo); break;
-        case 4: demap_store<4>(dst + l * 4, xo, vo); break;
-        case 6: demap_store<6>(dst + l * 6, xo, vo); break;
-        default: demap_store<8>(dst + l * 8, xo, vo); break;
-      }
+      vo[l] = ok ? sd * __builtin_amdgcn_rcpf(1.f - sd) : __builtin_inff();
+      xo[l] = ok ? x[l] : make_float2(__builtin_nanf(""), __builtin_nanf(""));
     }
+    emit_element<NL, CAP::store_floats>(g, u.llr, valid ? (d * g.n_sc + k) * NL * g.qm : -1, xo,
+                                        vo);
   }
 }
 
@@ -705,11 +880,11 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
     if (batch_pair_path(g, CAP::rows, CAP::fac)) {  // the host's tile widths fit
       float4* pair = reinterpret_cast<float4*>(
           rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
-      detect_tile_pair<NL, RXF>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
+      detect_tile_pair<NL, RXF, CAP::store_floats>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
       return;
     }
   }
-  detect_tile<NL, RXF>(u, g, k0, nk, jlo, nj, rows, tab);
+  detect_tile<NL, RXF, CAP::store_floats>(u, g, k0, nk, jlo, nj, rows, tab);
 }
 
 template <int MAXNL, int BLOCKS, int RXF>
