@@ -276,10 +276,27 @@ def slot_latency(torch, ranphy, shape, rx, pil, nvar, h_res, prec, path, scs_hz,
     graph.replay()
     torch.cuda.synchronize()
     same = bool(torch.equal(l1.view(torch.int32), ref.view(torch.int32)))
+    # the fixed cost of the two launch modes: two one-element kernels, eager and replayed
+    tiny = torch.zeros(1, device=dev)
+
+    def two_tiny():
+        tiny.add_(1.0)
+        tiny.mul_(0.5)
+
+    floor_eager = timed(two_tiny)
+    with torch.cuda.stream(side):
+        two_tiny()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        two_tiny()
+    floor_graph = timed(g2.replay)
     slot_us = 1000.0 * 15e3 / scs_hz  # 14-symbol slot: 1 ms at 15 kHz, 0.5 ms at 30 kHz
     return {"eager_us": round(eager_us, 2), "graph_us": round(graph_us, 2),
             "graph_matches_eager": same, "slot_duration_us": slot_us,
-            "data_re_per_slot": one.n_dsym * one.n_sc}
+            "data_re_per_slot": one.n_dsym * one.n_sc,
+            "two_empty_kernels_us": {"eager": round(floor_eager, 2), "graph": round(floor_graph, 2)}}
 
 
 def h2d_rate(torch, rx_host, ms_step, re, ranphy=None, shape=None, fused_step=None):

@@ -324,13 +324,14 @@ def test_reduced_precision_sinr_loss_64x16():
         say("; ".join(line))
 
 
-def ill_conditioned_case():
-    """Two slots at a matrix-core shape (16 Rx x 8 layers, full-resolution channel given):
-    slot 0 (s2 = 1e-6) holds i.i.d. subcarriers, near-collinear layers 1/2 (delta 1e-6) and
-    exactly collinear layers 1/2 (regularised by s2 alone); slot 1 (s2 = 0, zero forcing)
-    holds i.i.d. subcarriers, identical layers 4/5 (singular) and near-collinear layers 4/5
-    (delta 1e-4, kappa ~ 1e9)."""
-    shape = SlotShape(2, 14, 16, 8, 4, 4, 2, (2,), 2)
+def ill_conditioned_case(n_rx=16, n_layers=8):
+    """Two slots at a matrix-core shape (n_rx Rx x n_layers layers, full-resolution channel
+    given): slot 0 (s2 = 1e-6) holds i.i.d. subcarriers, near-collinear layers 1/2 (delta
+    1e-6) and exactly collinear layers 1/2 (regularised by s2 alone); slot 1 (s2 = 0, zero
+    forcing) holds i.i.d. subcarriers, identical layers 4/5 (singular) and near-collinear
+    layers 4/5 (delta 1e-4, kappa ~ 1e9)."""
+    comb = 4 if n_layers <= 8 else 8
+    shape = SlotShape(2, 14, n_rx, n_layers, 4, comb, 2, (2,), 2)
     nsc, NR, NL, ND = shape.n_sc, shape.n_rx, shape.n_layers, shape.n_dsym
     rng = np.random.default_rng(21)
     cn = lambda *sz: ((rng.standard_normal(sz) + 1j * rng.standard_normal(sz)) / np.sqrt(2))
@@ -353,15 +354,17 @@ def ill_conditioned_case():
     return shape, H[:, None], rx, nvar, kappa
 
 
+@pytest.mark.parametrize("dims", [(16, 8), (64, 16)])
 @pytest.mark.parametrize("prec", [ranphy.PREC_FP32, ranphy.PREC_FP16, ranphy.PREC_BF16])
-def test_fp64_route_for_ill_conditioned_grams(prec):
+def test_fp64_route_for_ill_conditioned_grams(prec, dims):
     # Subcarriers whose Gram condition estimate exceeds 1e6 (or whose FP32 elimination
     # fails) are solved in FP64 from the FP32 channel and samples.  Where kappa > 1e6 an FP32
     # solve is off by O(1) (forward-error bound 8 kappa Nl 2^-24 >> 1), so agreement with the
     # FP64 oracle to 1e-4 shows the FP64 route ran; exactly singular systems (zero forcing
-    # with identical layers) give NaN / +inf on both sides.
-    shape, h, rx, nvar, kappa = ill_conditioned_case()
-    say(f"ill-conditioned Grams prec={prec}: kappa per subcarrier "
+    # with identical layers) give NaN / +inf on both sides.  Also at the 64 x 16 workload's
+    # array size.
+    shape, h, rx, nvar, kappa = ill_conditioned_case(*dims)
+    say(f"ill-conditioned Grams {dims[0]}x{dims[1]} prec={prec}: kappa per subcarrier "
         f"{np.array2string(np.log10(kappa), precision=1, max_line_width=200)}")
     x, nv = ranphy.mmse_detect(shape, dev(rx), dev(h), dev(nvar), h_res=ranphy.H_FULL,
                                precision=prec)
