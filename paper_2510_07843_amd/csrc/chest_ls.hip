@@ -78,6 +78,64 @@ __global__ void __launch_bounds__(256) chest_pilot_kernel(Geom g, const float2* 
   }
 }
 
+// chest_pilot_kernel for power-of-two Nr >= 2 and Nl >= 2 on 16-byte aligned complex64
+// buffers (the usual arrays): the same values, with shifts in place of the index divisions
+// (the kernel is short, so its index arithmetic is a visible share of its time), each
+// thread loading two antennas and storing two layers per 16-byte access.
+template <int T>
+__global__ void __launch_bounds__(256) chest_pilot2_kernel(Geom g, const float2* __restrict__ rx,
+                                                           const float2* __restrict__ pil,
+                                                           float2* __restrict__ h, int lnr,
+                                                           int lnl) {
+  __shared__ float2 ys[T * 8 * (kMaxRx + 1)];
+  __shared__ float2 ps[T * kMaxLayers];
+  const int C = g.comb, lc = g.comb_log2, NR = 1 << lnr, NL = 1 << lnl;
+  const int j = blockIdx.x % g.n_pilot;
+  const int so = blockIdx.x / g.n_pilot;  // slot * n_occ + occasion
+  const int o = so % g.n_occ;
+  const int64_t slot = so / g.n_occ;
+  const int n_in = (T * C * NR) >> 1;  // antenna pairs
+  for (int f = threadIdx.x; f < n_in; f += 256) {
+    const int t = f >> (lc + lnr - 1);
+    const int c = (f >> (lnr - 1)) & (C - 1);
+    const int r = (f & ((NR >> 1) - 1)) << 1;
+    const int k = C * j + c;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k < g.n_sc)
+      v = *reinterpret_cast<const float4*>(
+          rx + ((slot * g.n_symb + g.sym0[o] + t) * g.n_sc + k) * NR + r);
+    float2* y = ys + (t * C + c) * (NR + 1) + r;
+    y[0] = make_float2(v.x, v.y);
+    y[1] = make_float2(v.z, v.w);
+  }
+  if (threadIdx.x < T * NL) {
+    const int t = threadIdx.x >> lnl, p = threadIdx.x & (NL - 1);
+    ps[threadIdx.x] = pil[(((int64_t)so * T + t) * g.n_pilot + j) * NL + p];
+  }
+  __syncthreads();
+  float4* __restrict__ dst = reinterpret_cast<float4*>(h + ((int64_t)so * g.n_pilot + j) * NR * NL);
+  for (int e = threadIdx.x; e < (NR * NL) >> 1; e += 256) {  // layer pairs
+    const int r = e >> (lnl - 1);
+    const int p = (e & ((NL >> 1) - 1)) << 1;
+    float2 v[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int c = (p + w) & (C - 1);
+      v[w] = make_float2(0.f, 0.f);
+      if (C * j + c < g.n_sc) {
+        float2 q[T], y[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          q[t] = ps[t * NL + p + w];
+          y[t] = ys[(t * C + c) * (NR + 1) + r];
+        }
+        v[w] = ls_pilot<T>(q, y);
+      }
+    }
+    dst[e] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+  }
+}
+
 // Pilot resolution for small arrays: one block per (slot, occasion, run of up to jb
 // consecutive pilot indices), so that every block has work for its 256 threads.  Pilots
 // j0 .. j0 + jb - 1 of every comb offset sit on the C jb contiguous subcarriers
@@ -180,7 +238,16 @@ hipError_t launch_chest_rxf(const Geom& g, const float2* rx, const float2* pilot
     jb = max(1, min(64, jb));
     const int nrun = (g.n_pilot + jb - 1) / jb;
     const dim3 pgrid((unsigned)((int64_t)g.n_slots * g.n_occ * nrun));
-    if (jb == 1) {
+    const bool pow2 = g.n_rx >= 2 && g.n_layers >= 2 && (g.n_rx & (g.n_rx - 1)) == 0 &&
+                      (g.n_layers & (g.n_layers - 1)) == 0;
+    const bool al16 = ((reinterpret_cast<uintptr_t>(rx) | reinterpret_cast<uintptr_t>(h)) & 15) == 0;
+    if (jb == 1 && RXF == 0 && pow2 && al16) {
+      const int lnr = __builtin_ctz(g.n_rx), lnl = __builtin_ctz(g.n_layers);
+      if (g.td == 1)
+        hipLaunchKernelGGL((chest_pilot2_kernel<1>), pgrid, block, 0, s, g, rx, pilots, h, lnr, lnl);
+      else
+        hipLaunchKernelGGL((chest_pilot2_kernel<2>), pgrid, block, 0, s, g, rx, pilots, h, lnr, lnl);
+    } else if (jb == 1) {
       if (g.td == 1)
         hipLaunchKernelGGL((chest_pilot_kernel<1, RXF>), pgrid, block, 0, s, g, rx, pilots, h);
       else
