@@ -61,6 +61,10 @@ struct TileCap<8, 3> {
   // multi-UE form keeps lane-by-lane stores: the record exchange's registers cost it more
   // (spills) than the scattered stores do (measured).
   static constexpr int store_floats = 0;
+  static constexpr bool multi_occ = false;
+  // received samples read by lane groups in whole 16-antenna lines (for_rx): the multi-UE
+  // launch 0.65 -> 0.59 ms (its 64-antenna UEs read 4 lines per element)
+  static constexpr bool line_loads = true;
 };
 template <>
 struct TileCap<4, 4> {  // two-occasion tiles of 16 x 4 fit 21 subcarriers
@@ -68,6 +72,8 @@ struct TileCap<4, 4> {  // two-occasion tiles of 16 x 4 fit 21 subcarriers
   static constexpr bool one_occ = false;
   static constexpr int stage_batch = 4;
   static constexpr int store_floats = 32;  // whole 128-byte records of 4 layers x 256QAM
+  static constexpr bool multi_occ = true;  // launched for two or more occasions only
+  static constexpr bool line_loads = true;
 };
 template <>
 struct TileCap<4, 5> {  // one-occasion tiles only
@@ -75,6 +81,8 @@ struct TileCap<4, 5> {  // one-occasion tiles only
   static constexpr bool one_occ = true;
   static constexpr int stage_batch = 1;  // within the 5-block register budget
   static constexpr int store_floats = 0;   // likewise (measured on the paper's 2x2 and 4x4)
+  static constexpr bool multi_occ = false;
+  static constexpr bool line_loads = false;  // its 96 registers: the group loads spill here
 };
 
 __host__ __device__ inline bool batch_pair_fits(const Geom& g, int rows, int nk, int cap_rows,

@@ -131,7 +131,7 @@ __device__ __forceinline__ void xpose_stage_quad(int (&c)[P][4], bool odd) {
   }
 }
 
-// Groups of P = 2, 4 or 8 lanes exchanging 16-byte chunks (store_records).  A
+// Groups of P = 2, 4 or 8 lanes exchanging 16-byte chunks (store_records, load_lines16).  A
 // lane's member index within its group takes bit 0 from lane bit 2, bit 1 from lane bit 3
 // and bit 2 from lane bit 0; ml(i) is the lane of member i.
 template <int P>
@@ -189,6 +189,61 @@ __device__ __forceinline__ void store_records(float* __restrict__ base, int off,
         reinterpret_cast<float2*>(dst)[1] = make_float2(v.z, v.w);
       }
     }
+  }
+}
+
+// The mirror of store_records for loads: each lane's 16 consecutive complex values from
+// base + off (its resource element's samples of 16 antennas, one 128-byte line) into y, read
+// so that load i fetches member i's whole line, one chunk per lane, and transposed back
+// within the groups of 8.  Every lane of the wave must call this with an in-range off.
+__device__ __forceinline__ void load_lines16(const float2* __restrict__ base, int off,
+                                             float2 (&y)[16]) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int me = group_member<8>(lane);
+  const bool wide = (reinterpret_cast<uintptr_t>(base) & 15) == 0;  // else 8-byte pieces
+  int c[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int oi = __builtin_amdgcn_ds_bpermute(group_lane<8>(lane, i) << 2, off);
+    const float2* src = base + oi + 2 * me;
+    float4 v;
+    if (wide) {
+      v = *reinterpret_cast<const float4*>(src);
+    } else {
+      const float2 a = src[0], b = src[1];
+      v = make_float4(a.x, a.y, b.x, b.y);
+    }
+    c[i][0] = __float_as_int(v.x);
+    c[i][1] = __float_as_int(v.y);
+    c[i][2] = __float_as_int(v.z);
+    c[i][3] = __float_as_int(v.w);
+  }
+  group_transpose<8>(c, lane);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    y[2 * i] = make_float2(__int_as_float(c[i][0]), __int_as_float(c[i][1]));
+    y[2 * i + 1] = make_float2(__int_as_float(c[i][2]), __int_as_float(c[i][3]));
+  }
+}
+
+// f(r, y_r) for the antennas r = 0 .. NR - 1 of one resource element (re: its index in the
+// slot's grid), the samples read by lane groups in whole 16-antenna lines where the grid is
+// complex64 and NR a multiple of 16 (each lane reading its own 16-byte pieces of 64
+// different lines would fetch a line's halves at different times, and L2 refetches some),
+// else lane by lane (LINES false: always, where the kernel form has no registers to spare).
+// Every lane of the wave must call this.
+template <int RXF, bool LINES, class F>
+__device__ __forceinline__ void for_rx(const BatchUe& u, int64_t re, int NR, F&& f) {
+  if (LINES && RXF == 0 && (NR & 15) == 0) {
+    for (int r0 = 0; r0 < NR; r0 += 16) {
+      float2 y[16];
+      load_lines16(u.rx, (int)(re * NR) + r0, y);
+#pragma unroll
+      for (int c = 0; c < 16; ++c) f(r0 + c, y[c]);
+    }
+  } else {
+#pragma unroll 8
+    for (int r = 0; r < NR; ++r) f(r, rx_at<RXF>(u.rx, re, NR, r));
   }
 }
 
@@ -385,7 +440,7 @@ __device__ __forceinline__ void detect_tile(const BatchUe& u, const Geom& g, int
 // once; float4 (H0, D) per antenna and layer in pair[]) and A, S, C (in gram[]); each
 // resource element then blends its Gram, forms z = (H0 + t D)^H y from the staged pairs and
 // finishes as the other paths do.
-template <int NL, int RXF, int MAXR>
+template <int NL, int RXF, int MAXR, bool LINES>
 __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g, int k0, int nk,
                                                  int jlo, int nj,
                                  const float2* __restrict__ rows, float4* __restrict__ pair,
@@ -488,16 +543,14 @@ __device__ __forceinline__ void detect_tile_pair(const BatchUe& u, const Geom& g
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
     const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
     const float4* q = pair + kk * PS;
-#pragma unroll 16
-    for (int r = 0; r < NR; ++r) {
-      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
+    for_rx<RXF, LINES>(u, re, NR, [&](int r, float2 y) {
 #pragma unroll
       for (int p = 0; p < NL; ++p) {
         const float4 v = q[r * NL + p];
         const float2 h = make_float2(v.x + t * v.z, v.y + t * v.w);
         cmac_c(z[p], h, y);
       }
-    }
+    });
     const float2* gg = gram + kk * GS;  // blended after the matched filter: fewer live values
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
@@ -640,13 +693,11 @@ __device__ __forceinline__ void detect_tile_fact(const BatchUe& u, const Geom& g
 #pragma unroll
     for (int i = 0; i < NL; ++i) z[i] = make_float2(0.f, 0.f);
     const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
-#pragma unroll 8
-    for (int r = 0; r < NR; ++r) {
-      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
+    for_rx<RXF, CAP::line_loads>(u, re, NR, [&](int r, float2 y) {
 #pragma unroll
       for (int i = 0; i < NL; ++i)
         cmac_c(z[i], row_interp(rows, RS, NL, r0[i], r1[i], a[i], r, i), y);
-    }
+    });
     const float2* L = fac + kk * CAP::fnp;
     const float* ax = aux + kk * CAP::aux;
     const bool ok = ax[2 * NL] != 0.f;
@@ -834,9 +885,7 @@ __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, i
     for (int i = 0; i < NL; ++i) x[i] = make_float2(0.f, 0.f);
     const int64_t re = (int64_t)tab.dsym[d] * g.n_sc + k;
     const float2* w = wf + kk * WS;
-#pragma unroll 8
-    for (int r = 0; r < NR; ++r) {
-      const float2 y = rx_at<RXF>(u.rx, re, NR, r);
+    for_rx<RXF, CAP::line_loads>(u, re, NR, [&](int r, float2 y) {
 #pragma unroll
       for (int l = 0; l < NL; ++l) {  // x_l += W[l][r] y_r
         const float2 c = w[r * NL + l];
@@ -845,7 +894,7 @@ __device__ __forceinline__ void detect_tile_w(const BatchUe& u, const Geom& g, i
         x[l].y = fmaf(c.x, y.y, x[l].y);
         x[l].y = fmaf(c.y, y.x, x[l].y);
       }
-    }
+    });
     float2 xo[NL];
     float vo[NL];
 #pragma unroll
@@ -866,6 +915,18 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
                                              SymTab& tab) {
   int jlo, nj;
   stage_pilots<CAP::stage_batch, RXF>(u, g, k0, nk, rows, tab, jlo, nj);
+  if constexpr (CAP::multi_occ) {  // launched for several occasions only
+    if constexpr (NL <= 4) {
+      float4* pair = reinterpret_cast<float4*>(
+          rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
+      if (batch_pair_path(g, CAP::rows, CAP::fac)) {
+        detect_tile_pair<NL, RXF, CAP::store_floats, CAP::line_loads>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
+        return;
+      }
+    }
+    detect_tile<NL, RXF, CAP::store_floats>(u, g, k0, nk, jlo, nj, rows, tab);
+    return;
+  }
   if (CAP::one_occ || g.n_occ == 1) {  // a one-occasion form is launched for those only
     factor_tile<NL, CAP>(u, g, k0, nk, jlo, rows, fac, aux);
     const int rs = batch_row_stride(g.n_rx, NL);
@@ -880,7 +941,7 @@ __device__ __forceinline__ void process_tile(const BatchUe& u, const Geom& g, in
     if (batch_pair_path(g, CAP::rows, CAP::fac)) {  // the host's tile widths fit
       float4* pair = reinterpret_cast<float4*>(
           rows + batch_pair_base(g.n_occ * nj, batch_row_stride(g.n_rx, NL)));
-      detect_tile_pair<NL, RXF, CAP::store_floats>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
+      detect_tile_pair<NL, RXF, CAP::store_floats, CAP::line_loads>(u, g, k0, nk, jlo, nj, rows, pair, fac, tab);
       return;
     }
   }
