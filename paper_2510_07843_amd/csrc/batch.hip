@@ -90,7 +90,7 @@ __device__ __forceinline__ void cmsb_c(float2& acc, float2 a, float2 b) {
   acc.y = fmaf(a.y, b.x, acc.y);
 }
 
-// One exchange stage of the in-group chunk transpose of store_records, for the member-index
+// One exchange stage of the in-group chunk transpose (group_transpose), for the member-index
 // bit S that lane bit LB carries (LB = 2 or 3: the partner lies 4 or 8 lanes away in the same
 // DPP row, and the DPP bank mask picks the lanes that take the moved value, so the stage is
 // one DPP move per value).  Members with the bit clear take the partner's chunk a into slot
@@ -133,7 +133,8 @@ __device__ __forceinline__ void xpose_stage_quad(int (&c)[P][4], bool odd) {
 
 // Groups of P = 2, 4 or 8 lanes exchanging 16-byte chunks (store_records, load_lines16).  A
 // lane's member index within its group takes bit 0 from lane bit 2, bit 1 from lane bit 3
-// and bit 2 from lane bit 0; ml(i) is the lane of member i.
+// and bit 2 from lane bit 0 (group_member); group_lane(lane, i) is the lane of member i of
+// lane's group.
 template <int P>
 __device__ __forceinline__ int group_member(int lane) {
   return ((lane >> 2) & 1) | (P >= 4 ? ((lane >> 3) & 1) << 1 : 0) |

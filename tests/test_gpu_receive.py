@@ -146,6 +146,26 @@ def test_receive_graph_replay():
         assert torch.equal(out.view(torch.int32), ref.view(torch.int32)), i
 
 
+@pytest.mark.parametrize("name", ["c2", "prb3_l2_r64_2occ", "prb9_l6_2occ_r40"])
+def test_receive_eight_byte_aligned_buffers(name):
+    # The received grid and the LLR buffer 8-byte but not 16-byte aligned (the library's
+    # minimum): the group line loads and record stores then move 8-byte pieces; the LLRs must
+    # equal those of 16-byte aligned buffers bit for bit, and the word before the LLRs must
+    # stay untouched.
+    shape = SHAPES[name]
+    rx, pil, nvar = make(shape, 5)
+    rxd, pild, nvd = dev(rx), dev(pil), dev(nvar)
+    ref = ranphy.receive(shape, rxd, pild, nvd)
+    rx_big = torch.empty(rxd.numel() + 1, dtype=torch.complex64, device="cuda")
+    rx_big[1:] = rxd
+    llr_big = torch.full((ref.numel() + 2,), 7.0, dtype=torch.float32, device="cuda")
+    assert (rx_big[1:].data_ptr() % 16, llr_big[2:].data_ptr() % 16) == (8, 8)
+    ranphy.receive(shape, rx_big[1:], pild, nvd, llr=llr_big[2:])
+    torch.cuda.synchronize()
+    assert torch.equal(llr_big[2:].view(torch.int32), ref.view(torch.int32))
+    assert llr_big[:2].tolist() == [7.0, 7.0]
+
+
 @pytest.mark.parametrize("cfg", ["c2", "p8"])
 def test_receive_full_size_sampled(cfg):
     # The configuration at the slot count the benchmark times; the oracle chain on a sample
