@@ -115,6 +115,31 @@ def test_batch_graph_replay_and_grid_independence():
             assert torch.equal(u["llr"].view(torch.int32), r.view(torch.int32)), rep
 
 
+def test_batch_eight_byte_aligned_grids():
+    # UEs whose received grid sits 8 bytes past a 16-byte boundary (the library's minimum
+    # alignment) take the 8-byte pieces of the group line loads; their LLRs must equal those
+    # of the same UEs with aligned grids bit for bit.
+    ues = make_ues(8, seed=4, max_prb=16)
+    b = ranphy.Batch(ues, tile_re=512)
+    b.run(256)
+    torch.cuda.synchronize()
+    ref = [u["llr"].clone() for u in ues]
+    keep = []
+    for u in ues:
+        big = torch.empty(u["rx"].numel() + 1, dtype=torch.complex64, device="cuda")
+        big[1:] = u["rx"]
+        keep.append(big)
+        u["rx"] = big[1:]
+        assert u["rx"].data_ptr() % 16 == 8
+        u["llr"] = None
+    b2 = ranphy.Batch(ues, tile_re=512)
+    b2.run(256)
+    torch.cuda.synchronize()
+    assert any(u["shape"].n_rx % 16 == 0 for u in ues)
+    for u, r in zip(ues, ref):
+        assert torch.equal(u["llr"].view(torch.int32), r.view(torch.int32))
+
+
 def test_autotune_returns_a_valid_configuration():
     ues = make_ues(12, seed=3, max_prb=32)
     res = tune.autotune(ues, tiles=(256, 1024), blocks_per_cu=(1, 3), reps=2)
