@@ -175,21 +175,27 @@ __device__ __forceinline__ void store_records(float* __restrict__ base, int off,
 #pragma unroll
     for (int q = 0; q < 4; ++q) c[i][q] = i < NC ? __float_as_int(out[4 * i + q]) : 0;
   group_transpose<P>(c, lane);
-  const bool wide = (reinterpret_cast<uintptr_t>(base) & 15) == 0;  // else 8-byte pieces
+  int oi[P];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const int oi = __builtin_amdgcn_ds_bpermute(group_lane<P>(lane, i) << 2, off);
-    if (oi >= 0 && me < NC) {
-      float* dst = base + oi + 4 * me;
-      const float4 v = make_float4(__int_as_float(c[i][0]), __int_as_float(c[i][1]),
-                                   __int_as_float(c[i][2]), __int_as_float(c[i][3]));
-      if (wide) {
-        *reinterpret_cast<float4*>(dst) = v;
-      } else {
-        reinterpret_cast<float2*>(dst)[0] = make_float2(v.x, v.y);
-        reinterpret_cast<float2*>(dst)[1] = make_float2(v.z, v.w);
+  for (int i = 0; i < P; ++i) oi[i] = __builtin_amdgcn_ds_bpermute(group_lane<P>(lane, i) << 2, off);
+  // 16-byte pieces where the buffer allows (the branch is uniform; the two store loops are
+  // kept apart so that each compiles to its own access width)
+  if ((reinterpret_cast<uintptr_t>(base) & 15) == 0) {
+    float4* __restrict__ b4 = reinterpret_cast<float4*>(base);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (oi[i] >= 0 && me < NC)
+        b4[(oi[i] >> 2) + me] = make_float4(__int_as_float(c[i][0]), __int_as_float(c[i][1]),
+                                            __int_as_float(c[i][2]), __int_as_float(c[i][3]));
+  } else {
+    float2* __restrict__ b2 = reinterpret_cast<float2*>(base);
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+      if (oi[i] >= 0 && me < NC) {
+        b2[(oi[i] >> 1) + 2 * me] = make_float2(__int_as_float(c[i][0]), __int_as_float(c[i][1]));
+        b2[(oi[i] >> 1) + 2 * me + 1] =
+            make_float2(__int_as_float(c[i][2]), __int_as_float(c[i][3]));
       }
-    }
   }
 }
 
@@ -201,23 +207,29 @@ __device__ __forceinline__ void load_lines16(const float2* __restrict__ base, in
                                              float2 (&y)[16]) {
   const int lane = (int)(threadIdx.x & 63);
   const int me = group_member<8>(lane);
-  const bool wide = (reinterpret_cast<uintptr_t>(base) & 15) == 0;  // else 8-byte pieces
-  int c[8][4];
+  int oi[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int oi = __builtin_amdgcn_ds_bpermute(group_lane<8>(lane, i) << 2, off);
-    const float2* src = base + oi + 2 * me;
-    float4 v;
-    if (wide) {
-      v = *reinterpret_cast<const float4*>(src);
-    } else {
-      const float2 a = src[0], b = src[1];
-      v = make_float4(a.x, a.y, b.x, b.y);
+  for (int i = 0; i < 8; ++i) oi[i] = __builtin_amdgcn_ds_bpermute(group_lane<8>(lane, i) << 2, off);
+  int c[8][4];
+  if ((reinterpret_cast<uintptr_t>(base) & 15) == 0) {  // 16-byte pieces (uniform branch)
+    const float4* __restrict__ b4 = reinterpret_cast<const float4*>(base);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float4 v = b4[(oi[i] >> 1) + me];
+      c[i][0] = __float_as_int(v.x);
+      c[i][1] = __float_as_int(v.y);
+      c[i][2] = __float_as_int(v.z);
+      c[i][3] = __float_as_int(v.w);
     }
-    c[i][0] = __float_as_int(v.x);
-    c[i][1] = __float_as_int(v.y);
-    c[i][2] = __float_as_int(v.z);
-    c[i][3] = __float_as_int(v.w);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float2 a = base[oi[i] + 2 * me], b = base[oi[i] + 2 * me + 1];
+      c[i][0] = __float_as_int(a.x);
+      c[i][1] = __float_as_int(a.y);
+      c[i][2] = __float_as_int(b.x);
+      c[i][3] = __float_as_int(b.y);
+    }
   }
   group_transpose<8>(c, lane);
 #pragma unroll
