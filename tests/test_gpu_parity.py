@@ -550,17 +550,17 @@ def test_llr_demap_8_byte_aligned_buffers():
     assert llr_tol_ok(lg, lr).all()
 
 
-def test_fused_64x16_bench_launch_sampled():
-    # The launch the benchmark times: chest_ls -> mmse_llr over 140 slots of 64 Rx x 16
-    # layers (3.29 GB of samples, 2.11 GB of LLRs, element offsets past 2^31 bytes), once;
-    # its first, middle and last slots (the benchmark's own slots, drawn from their seeds)
-    # against the oracle chain.  The other slots repeat those three.
+@pytest.fixture(scope="module")
+def bench_launch():
+    """The input of the launch the benchmark times: 140 slots of 64 Rx x 16 layers (3.29 GB
+    of samples, 2.11 GB of LLRs, element offsets past 2^31 bytes) with the pilot-resolution
+    estimate; its first, middle and last slots are the benchmark's own slots, drawn from
+    their seeds, and the other slots repeat those three."""
     c = synth.CONFIGS["m"]
     S = len(c["snr_db"]) * c["slots_per_snr"]
     shape = c["shape"].with_slots(S)
     picks = [0, S // 2, S - 1]
     slots = {i: synth.batch_slot("m", i) for i in picks}
-    say(f"64x16 bench launch: {S} slots, checking {picks}")
     one = shape.with_slots(1)
     rx = torch.empty((S, one.n_symb * one.n_sc * one.n_rx), dtype=torch.complex64, device="cuda")
     pil = torch.empty((S, one.n_occ * one.dmrs_td * one.n_pilot * one.n_layers),
@@ -572,7 +572,26 @@ def test_fused_64x16_bench_launch_sampled():
         pil[s] = torch.from_numpy(d["pilots"].reshape(-1)).cuda()
         nvar[s] = float(np.float32(d["noise_var"]))
     h = ranphy.chest_ls(shape, rx.reshape(-1), pil.reshape(-1))
-    llr = ranphy.mmse_llr(shape, rx.reshape(-1), h, nvar)
+    # the oracle's estimate of the same slots, for the variants fed an oracle-made channel
+    h_or = {i: oracle.chest_ls(one, slots[i]["rx"][None], slots[i]["pilots"][None]).astype(
+        np.complex64) for i in picks}
+    ho = torch.empty((S, h.numel() // S), dtype=torch.complex64, device="cuda")
+    for s in range(S):
+        ho[s] = torch.from_numpy(h_or[picks[s % 3]] if s not in h_or else h_or[s]).cuda().reshape(-1)
+    torch.cuda.synchronize()
+    yield dict(shape=shape, one=one, S=S, picks=picks, slots=slots, rx=rx, nvar=nvar, h=h,
+               h_or=h_or, ho=ho)
+    del rx, pil, nvar, h, ho
+    torch.cuda.empty_cache()
+
+
+def test_fused_64x16_bench_launch_sampled(bench_launch):
+    # The launch the benchmark times, chest_ls -> mmse_llr over the 140 slots, once; its
+    # first, middle and last slots against the oracle chain.
+    b = bench_launch
+    shape, one, S, picks, slots = b["shape"], b["one"], b["S"], b["picks"], b["slots"]
+    say(f"64x16 bench launch: {S} slots, checking {picks}")
+    llr = ranphy.mmse_llr(shape, b["rx"].reshape(-1), b["h"], b["nvar"])
     torch.cuda.synchronize()
     llr = llr.reshape(S, -1)
     lq = (1, one.n_dsym, one.n_sc, one.n_layers, one.qm)
@@ -588,6 +607,40 @@ def test_fused_64x16_bench_launch_sampled():
         parity.audit_llrs(lg, lr, xr, nvr,
                           parity.kappa_radius(grams, xr.reshape(-1, one.n_layers), one.n_layers),
                           one.qm, f"bench launch slot {s}")
+
+
+@pytest.mark.parametrize("pn", ["fp16", "bf16"])
+def test_fused_64x16_bench_launch_sampled_16bit(bench_launch, pn):
+    # The benchmark's 16-bit variants over the same 140-slot launch: the first, middle and
+    # last slots against the oracle run on the inputs rounded to the 16-bit type as the kernel
+    # rounds them (channel interpolated in FP32, then rounded; samples rounded; unit-power
+    # inputs need no FP16 scaling), every LLR to the FP32 bars (what remains is FP32
+    # accumulation and inversion).
+    prec = ranphy.PREC_FP16 if pn == "fp16" else ranphy.PREC_BF16
+    p = parity.SIG_BITS[pn]
+    b = bench_launch
+    shape, one, S, picks, slots = b["shape"], b["one"], b["S"], b["picks"], b["slots"]
+    say(f"64x16 bench launch {pn}: {S} slots, checking {picks}")
+    # both sides take the oracle's channel estimate of the slots
+    llr = ranphy.mmse_llr(shape, b["rx"].reshape(-1), b["ho"].reshape(-1), b["nvar"],
+                          precision=prec)
+    torch.cuda.synchronize()
+    llr = llr.reshape(S, -1)
+    lq = (1, one.n_dsym, one.n_sc, one.n_layers, one.qm)
+    for s in picks:
+        d = slots[s]
+        rxh = d["rx"][None]
+        nvh = np.array([d["noise_var"]], np.float32)
+        hk = parity.fp32_interpolated_channel(one, b["h_or"][s])
+        hq = parity.round_complex(hk, p)[:, None]
+        rxq = parity.round_complex(rxh, p)
+        xq, nvq = oracle.mmse_detect(one, rxq, hq, ranphy.H_FULL, nvh)
+        lr = oracle.llr_demap(one, xq.astype(np.complex64), nvq.astype(np.float32))
+        lg = llr[s].cpu().numpy().reshape(lq)
+        grams = parity.gram_fn(one, hq, ranphy.H_FULL, nvh)
+        parity.audit_llrs(lg, lr, xq, nvq,
+                          parity.kappa_radius(grams, xq.reshape(-1, one.n_layers), one.n_layers),
+                          one.qm, f"bench launch {pn} slot {s}")
 
 
 PREC_NAME = {ranphy.PREC_FP16: "fp16", ranphy.PREC_BF16: "bf16"}
