@@ -643,6 +643,69 @@ def test_fused_64x16_bench_launch_sampled_16bit(bench_launch, pn):
                           one.qm, f"bench launch {pn} slot {s}")
 
 
+@pytest.mark.parametrize("pn", ["fp16", "bf16"])
+def test_fused_64x16_bench_launch_sampled_refined(bench_launch, pn):
+    # The refined variants over the same 140-slot launch (both sides fed the oracle's channel
+    # estimate): in the first, middle and last slots every (RE, layer) of x~ and nu2 within
+    # parity.refined_bound plus the FP32 forward-error bound of the oracle on the exact
+    # inputs, every LLR inside the range the oracle's LLR takes over that error ball, and the
+    # refined EVM at least 10 dB below the unrefined mode's.
+    prec = ranphy.PREC_FP16_REFINED if pn == "fp16" else ranphy.PREC_BF16_REFINED
+    base = ranphy.PREC_FP16 if pn == "fp16" else ranphy.PREC_BF16
+    p = parity.SIG_BITS[pn]
+    b = bench_launch
+    shape, one, S, picks, slots = b["shape"], b["one"], b["S"], b["picks"], b["slots"]
+    say(f"64x16 bench launch {pn} refined: {S} slots, checking {picks}")
+    rxf, hof = b["rx"].reshape(-1), b["ho"].reshape(-1)
+    x1, v1 = ranphy.mmse_detect(shape, rxf, hof, b["nvar"], precision=prec)
+    lf = ranphy.mmse_llr(shape, rxf, hof, b["nvar"], precision=prec)
+    x0, _ = ranphy.mmse_detect(shape, rxf, hof, b["nvar"], precision=base)
+    torch.cuda.synchronize()
+    NL, NR = one.n_layers, one.n_rx
+    oq = (1, one.n_dsym, one.n_sc, NL)
+    x1, v1, x0, lf = (t.reshape(S, -1) for t in (x1, v1, x0, lf))
+    ds = one.data_symbols()
+    for s in picks:
+        d = slots[s]
+        rxh = d["rx"][None]
+        nvh = np.array([d["noise_var"]], np.float32)
+        hk = parity.fp32_interpolated_channel(one, b["h_or"][s])
+        xr, nvr = oracle.mmse_detect(one, rxh, hk[:, None], ranphy.H_FULL, nvh)
+        lr = oracle.llr_demap(one, xr.astype(np.complex64), nvr.astype(np.float32))
+        xg = x1[s].cpu().numpy().reshape(oq)
+        nvg = v1[s].cpu().numpy().reshape(oq)
+        xb = x0[s].cpu().numpy().reshape(oq)
+        lg = lf[s].cpu().numpy().reshape(oq + (one.qm,))
+        nd_, nsc = one.n_dsym, one.n_sc
+        Hre = np.broadcast_to(hk[:, None].astype(np.complex128), (1, nd_) + hk.shape[1:])
+        y = rxh[:, ds].astype(np.complex128)
+        s2 = np.full(nd_ * nsc, float(nvh[0]))
+        bx, bv, valid = parity.refined_bound(Hre.reshape(-1, NR, NL), y.reshape(-1, NR),
+                                             xr.reshape(-1, NL), nvr.reshape(-1, NL), s2, p)
+        grams = parity.gram_fn(one, hk[:, None], ranphy.H_FULL, nvh)
+        kd = parity.kappa_delta(grams(np.arange(nd_ * nsc)), NL)
+        f32 = kd[:, None] * np.linalg.norm(xr.reshape(-1, NL), axis=1)[:, None]
+        dx = np.abs(xg.reshape(-1, NL) - xr.reshape(-1, NL))
+        dv = np.abs(nvg.reshape(-1, NL) - nvr.reshape(-1, NL))
+        ok = (dx <= bx + f32) & (dv <= bv + kd[:, None] * np.abs(nvr.reshape(-1, NL)))
+        assert valid.mean() > 0.99, (s, valid.mean())
+        assert ok[valid].all(), (s, np.argwhere(~ok & valid[:, None])[:5])
+
+        def radius(idx):
+            re_idx, l = idx // NL, idx % NL
+            return bx[re_idx, l] + f32[re_idx, 0], bv[re_idx, l] / np.maximum(
+                np.abs(nvr.reshape(-1)[idx]), 1e-30) + kd[re_idx]
+
+        parity.audit_llrs(lg, lr, xr, nvr, radius, one.qm, f"bench launch {pn} refined slot {s}")
+
+        def evm(a):
+            return 10 * np.log10(np.mean(np.abs(a - xr) ** 2) / np.mean(np.abs(xr) ** 2))
+
+        e1, e0 = evm(xg), evm(xb)
+        say(f"  slot {s}: EVM vs exact-input oracle unrefined {e0:.1f} dB, refined {e1:.1f} dB")
+        assert e1 < e0 - 10.0, (s, e0, e1)
+
+
 PREC_NAME = {ranphy.PREC_FP16: "fp16", ranphy.PREC_BF16: "bf16"}
 
 
