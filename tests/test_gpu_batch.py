@@ -81,6 +81,49 @@ def test_batch_matches_oracle_per_ue():
                                  f"occ {sh.dmrs_sym0}")
 
 
+def test_batch_bench_workload_sampled():
+    # The 200-UE workload the benchmark times, at the plan its profiles use (tile of 2048
+    # REs, 3 blocks per compute unit; other tiles give the same bits, test below) and replayed
+    # from a HIP graph as the benchmark does; a sample of UEs against the oracle chain: the
+    # first, middle and last, the largest allocation, and the first UE of one layer and of
+    # eight.
+    import bench
+    ues = bench.make_batch_ues(torch, synth, n_ue=200)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    b = ranphy.Batch(ues, tile_re=2048)
+    say(f"bench batch: {len(ues)} UEs, {b.n_items} work items, {3 * cus} blocks")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.run(3 * cus)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    ref = [u["llr"].clone() for u in ues]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.run(3 * cus)
+    for u in ues:
+        u["llr"].fill_(-3.0)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for u, r in zip(ues, ref):
+        assert torch.equal(u["llr"].view(torch.int32), r.view(torch.int32))
+    pick = {0, len(ues) // 2, len(ues) - 1,
+            max(range(len(ues)), key=lambda i: ues[i]["shape"].n_prb * ues[i]["shape"].n_rx)}
+    for nl in (1, 8):
+        pick.add(next(i for i, u in enumerate(ues) if u["shape"].n_layers == nl))
+    for i in sorted(pick):
+        u = ues[i]
+        sh = u["shape"]
+        lg = u["llr"].cpu().numpy().reshape(1, sh.n_dsym, sh.n_sc, sh.n_layers, sh.qm)
+        hr, xr, nvr, lr = oracle_ref(u)
+        grams = parity.gram_fn(sh, hr, oracle.H_PILOT, u["nv_h"])
+        parity.audit_llrs(lg, lr, xr, nvr,
+                          parity.kappa_radius(grams, xr.reshape(-1, sh.n_layers), sh.n_layers),
+                          sh.qm, f"bench UE {i}: {sh.n_prb} PRB {sh.n_rx}x{sh.n_layers} qm {sh.qm}")
+
+
 def test_batch_graph_replay_and_grid_independence():
     ues = make_ues(10, seed=2, max_prb=24)
     b = ranphy.Batch(ues, tile_re=256)
